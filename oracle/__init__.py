@@ -1,0 +1,169 @@
+"""FP64 CPU oracle for the block-floating-point FFT and range-Doppler SAR path.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of ``bench.py``; never by the product package.  It shares
+no code with the GPU path.  Inputs are numpy ``complex128`` arrays (callers
+pass the storage-rounded values, which are exact in FP64).
+
+Every function evaluates the plain mathematical definition (paper Sec. III-B
+and Eq. (1)); see ``oracle.c`` for the algorithms.  The block-floating-point
+shift is a mathematical no-op, so the oracle computes the exact linear maps.
+
+Parity status of each function is recorded in ``tests/test_oracle.py``; the
+FP16/FP8 emulator in ``emulator.py`` reproduces Tables I and V of the paper.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        lib = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L = ctypes.c_long
+        lib.oracle_fft_rows.argtypes = [dp, dp, L, L, ctypes.c_int]
+        lib.oracle_dft_direct.argtypes = [dp, dp, L, ctypes.c_int]
+        lib.oracle_root.argtypes = [ctypes.c_longlong, ctypes.c_longlong, dp, dp]
+        lib.oracle_matched_filter.argtypes = [dp, L, L, dp]
+        lib.oracle_compress_rows.argtypes = [dp, dp, dp, L, L, ctypes.c_int]
+        lib.oracle_transpose.argtypes = [dp, dp, L, L]
+        lib.oracle_apply_phase.argtypes = [dp, dp, dp, L, L]
+        lib.oracle_sar_image.argtypes = [dp, L, L, dp, dp, dp, dp, dp]
+        lib.oracle_entropy.argtypes = [dp, L, dp]
+        lib.oracle_entropy.restype = ctypes.c_double
+        lib.oracle_autofocus.argtypes = [dp, L, L, dp, dp, dp, dp]
+        lib.oracle_autofocus.restype = ctypes.c_double
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    _load().oracle_set_threads(int(n))
+
+
+def fft(x, inverse: bool = False):
+    """Row-wise forward DFT (unscaled) or normalised inverse over the last axis."""
+    x = _c128(x)
+    n = x.shape[-1]
+    out = np.empty_like(x)
+    rows = x.size // n if n else 0
+    if _load().oracle_fft_rows(_ptr(x), _ptr(out), rows, n, int(inverse)) != 0:
+        raise ValueError("length must be a power of two")
+    return out
+
+
+def dft_direct(x, inverse: bool = False):
+    """Brute-force O(N^2) DFT of a 1-D vector of any length."""
+    x = _c128(x).reshape(-1)
+    out = np.empty_like(x)
+    if _load().oracle_dft_direct(_ptr(x), _ptr(out), x.size, int(inverse)) != 0:
+        raise ValueError("empty input")
+    return out
+
+
+def root(k: int, n: int) -> complex:
+    """exp(-2 pi i k / n) as evaluated by the oracle (exact argument reduction)."""
+    re = ctypes.c_double()
+    im = ctypes.c_double()
+    _load().oracle_root(k, n, ctypes.byref(re), ctypes.byref(im))
+    return complex(re.value, im.value)
+
+
+def matched_filter(h, n: int):
+    """H = conj(DFT_n(h)) / max|DFT_n(h)| for a replica h zero-padded to n."""
+    h = _c128(h).reshape(-1)
+    H = np.empty(n, dtype=np.complex128)
+    if _load().oracle_matched_filter(_ptr(h), h.size, n, _ptr(H)) != 0:
+        raise ValueError("bad filter length")
+    return H
+
+
+def compress(x, H, conj_filter: bool = False):
+    """Row-wise y = IDFT(DFT(x) . H) (conj(H) when conj_filter)."""
+    x = _c128(x)
+    n = x.shape[-1]
+    H = _c128(H).reshape(-1)
+    assert H.size == n
+    out = np.empty_like(x)
+    if _load().oracle_compress_rows(_ptr(x), _ptr(out), _ptr(H), x.size // n, n,
+                                    int(conj_filter)) != 0:
+        raise ValueError("length must be a power of two")
+    return out
+
+
+def transpose(x):
+    x = _c128(x)
+    r, c = x.shape
+    out = np.empty((c, r), dtype=np.complex128)
+    _load().oracle_transpose(_ptr(x), _ptr(out), r, c)
+    return out
+
+
+def sar_image(echo, Hr, Ha, phi=None, return_rc=False):
+    """Range-Doppler image [range][azimuth] of an echo [pulse][range]."""
+    echo = _c128(echo)
+    n_pulse, n_range = echo.shape
+    Hr = _c128(Hr).reshape(-1)
+    Ha = _c128(Ha).reshape(-1)
+    assert Hr.size == n_range and Ha.size == n_pulse
+    img = np.empty((n_range, n_pulse), dtype=np.complex128)
+    rct = np.empty((n_range, n_pulse), dtype=np.complex128) if return_rc else None
+    ph = None if phi is None else np.ascontiguousarray(phi, dtype=np.float64)
+    if ph is not None:
+        assert ph.size == n_pulse
+    if _load().oracle_sar_image(_ptr(echo), n_pulse, n_range, _ptr(Hr), _ptr(Ha),
+                                _ptr(ph), _ptr(img), _ptr(rct)) != 0:
+        raise ValueError("sizes must be powers of two")
+    return (img, rct) if return_rc else img
+
+
+def apply_phase(rc_t, phi):
+    rc_t = _c128(rc_t)
+    nr, npul = rc_t.shape
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    out = np.empty_like(rc_t)
+    _load().oracle_apply_phase(_ptr(rc_t), _ptr(out), _ptr(ph), nr, npul)
+    return out
+
+
+def entropy(img, want_grad: bool = False):
+    img = _c128(img)
+    g = np.empty_like(img) if want_grad else None
+    E = _load().oracle_entropy(_ptr(img), img.size, _ptr(g))
+    return (E, g) if want_grad else E
+
+
+def autofocus(rc_t, Ha, phi, want_image: bool = False):
+    """Entropy E of A_az(rc_t . e^{i phi}) and its analytic gradient dE/dphi."""
+    rc_t = _c128(rc_t)
+    nr, npul = rc_t.shape
+    Ha = _c128(Ha).reshape(-1)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    g = np.empty(npul, dtype=np.float64)
+    img = np.empty_like(rc_t) if want_image else None
+    E = _load().oracle_autofocus(_ptr(rc_t), nr, npul, _ptr(Ha), _ptr(ph), _ptr(g), _ptr(img))
+    return (E, g, img) if want_image else (E, g)

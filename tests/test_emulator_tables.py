@@ -1,0 +1,75 @@
+"""The CPU FP16/FP8 emulator reproduces the paper's printed tables.
+
+These pins fix the SQNR definition (pooled energy, FP64 reference on the
+unquantised draw) and the rounding model that the GPU numbers are compared
+under.  Printed values: Table I (Sec. III-A) and Table V (Sec. VI); the
+fixtures live in tests/golden/ with their citations.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import emulator
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("n", [1024, 4096])
+@pytest.mark.parametrize("butterfly", ["standard", "fma6"])
+def test_table1_fp16_fft_sqnr(n, butterfly):
+    t = _load("table1_fp16_fft_sqnr.json")
+    paper = t["values"][butterfly][str(n)]
+    got = emulator.table1_sqnr(n, butterfly, trials=200)
+    assert abs(got - paper) <= t["tolerance_db"], (got, paper)
+
+
+@pytest.mark.parametrize("n", [1024, 4096])
+@pytest.mark.parametrize("fmt", ["fp16", "e4m3", "e5m2"])
+def test_table5_storage_sqnr(n, fmt):
+    t = _load("table5_storage_sqnr.json")
+    paper = t["values"][fmt][str(n)]
+    got = emulator.table5_sqnr(n, fmt, trials=200)
+    assert abs(got - paper) <= t["tolerance_db"][fmt], (got, paper)
+
+
+def test_storage_noise_model():
+    # one RNE storage rounding of a unit-variance complex value adds noise of
+    # variance ~ 2 * (2^-11)^2 / 3 * E[x^2 scale]; each radix-2 stage adds one.
+    # Closed form (sanity): SQNR ~ 73.5 - 10 log10(log2 N + 1) dB, within 0.5 dB.
+    for n in (1024, 4096):
+        got = emulator.table5_sqnr(n, "fp16", trials=50)
+        model = 73.5 - 10 * np.log10(np.log2(n) + 1)
+        assert abs(got - model) < 0.5
+
+
+def test_naive_fp16_chain_overflows_bfp_chain_does_not():
+    # Sec. III-B / Eq. (1): unscaled conj-FFT-conj inverse overflows FP16 on
+    # the Zadoff-Chu matched filter; folding 2^-log2N into the conjugate fixes it
+    n = 4096
+    m = np.arange(n)
+    x = np.exp(-1j * np.pi * ((m * m) % (2 * n)) / n)
+    X = oracle.fft(x[None])[0]
+    H = np.conj(X) / np.sqrt(n)
+    y_bfp = emulator.fp16_compress(x, H, bfp=True)
+    y_naive = emulator.fp16_compress(x, H, bfp=False)
+    assert np.all(np.isfinite(y_bfp))
+    assert abs(np.abs(y_bfp[0, 0]) - np.sqrt(n)) < 0.05
+    assert not np.all(np.isfinite(y_naive))
+
+
+def test_fp16_emulator_is_exact_on_dc():
+    # DC and alternating inputs are exact in every butterfly-decomposed FP16 FFT
+    n = 4096
+    for butterfly in ("standard", "fma6"):
+        y = emulator.fp16_radix2_fft(np.ones((1, n)), butterfly)[0]
+        assert y[0] == n and np.all(y[1:] == 0)
+        a = emulator.fp16_radix2_fft(((-1.0) ** np.arange(n))[None], butterfly)[0]
+        assert a[n // 2] == n and np.count_nonzero(a) == 1

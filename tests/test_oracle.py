@@ -1,0 +1,237 @@
+"""Pins of the FP64 oracle against facts fixed by mathematics and by the paper.
+
+Each test names the property it pins.  A plausible mistake in the oracle (a
+dropped term, a wrong sign or index, a transposed operand, a wrong scale)
+fails at least one of them:
+
+* brute force: recursive FFT == direct O(N^2) DFT for every N = 2..512;
+* library routine: == numpy.fft (pocketfft), an independent implementation;
+* invariants: Parseval, inverse round trip, linearity;
+* closed forms: DC, alternating, impulse, the quadratic Gauss sum;
+* the paper's overflow mechanism (Sec. III-B) and BFP fix (Eq. (1));
+* adjoint identity and entropy-gradient invariance for autofocus.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_28451_amd import scenes
+
+
+def _rand(rows, n, seed):
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((2, rows, n))
+    return g[0] + 1j * g[1]
+
+
+@pytest.mark.parametrize("n", [2 ** k for k in range(1, 10)])
+def test_fft_matches_direct_dft(n):
+    x = _rand(1, n, n)[0]
+    X = oracle.fft(x[None])[0]
+    D = oracle.dft_direct(x)
+    assert np.max(np.abs(X - D)) <= 1e-12 * n * np.max(np.abs(x))
+    Xi = oracle.fft(x[None], inverse=True)[0]
+    Di = oracle.dft_direct(x, inverse=True)
+    assert np.max(np.abs(Xi - Di)) <= 1e-12 * np.max(np.abs(x))
+
+
+def test_direct_dft_odd_length_closed_form():
+    # a non-power-of-two length exercises the exact argument reduction
+    n = 12
+    x = np.zeros(n, complex)
+    x[5] = 1.0
+    D = oracle.dft_direct(x)
+    k = np.arange(n)
+    assert np.allclose(D, np.exp(-2j * np.pi * 5 * k / n), atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [8, 256, 4096, 16384])
+def test_fft_matches_numpy(n):
+    x = _rand(3, n, 7)
+    X = oracle.fft(x)
+    ref = np.fft.fft(x, axis=-1)
+    rel = np.linalg.norm(X - ref) / np.linalg.norm(ref)
+    assert rel <= 1e-13
+
+
+@pytest.mark.parametrize("n", [64, 4096])
+def test_parseval_and_round_trip(n):
+    x = _rand(4, n, 11)
+    X = oracle.fft(x)
+    assert abs(np.sum(np.abs(X) ** 2) - n * np.sum(np.abs(x) ** 2)) <= 1e-13 * n * np.sum(np.abs(x) ** 2)
+    back = oracle.fft(X, inverse=True)
+    assert np.max(np.abs(back - x)) <= 1e-14 * np.max(np.abs(x)) * np.log2(n)
+
+
+def test_linearity():
+    n = 1024
+    a, b = _rand(2, n, 3)
+    lhs = oracle.fft((2.5 * a - 1j * b)[None])[0]
+    rhs = 2.5 * oracle.fft(a[None])[0] - 1j * oracle.fft(b[None])[0]
+    assert np.max(np.abs(lhs - rhs)) < 1e-10
+
+
+@pytest.mark.parametrize("n", [256, 4096, 16384])
+def test_dc_and_alternating_exact(n):
+    # all-ones -> N delta[k]; (-1)^n -> N delta[k - N/2]; exact in FP64
+    x = np.ones((1, n), complex)
+    X = oracle.fft(x)[0]
+    expect = np.zeros(n, complex)
+    expect[0] = n
+    assert np.array_equal(X, expect)
+    alt = ((-1.0) ** np.arange(n))[None].astype(complex)
+    A = oracle.fft(alt)[0]
+    expect = np.zeros(n, complex)
+    expect[n // 2] = n
+    assert np.array_equal(A, expect)
+
+
+@pytest.mark.parametrize("n0", [0, 1, 1000, 4095])
+def test_impulse_closed_form(n0):
+    n = 4096
+    x = np.zeros((1, n), complex)
+    x[0, n0] = 1.0
+    X = oracle.fft(x)[0]
+    k = np.arange(n)
+    assert np.max(np.abs(X - np.exp(-2j * np.pi * ((n0 * k) % n) / n))) < 1e-13
+
+
+def test_roots_exact_at_quarter_turns():
+    for n in (4, 256, 4096, 16384):
+        assert oracle.root(0, n) == complex(1, 0)
+        assert oracle.root(n // 4, n) == complex(0, -1)
+        assert oracle.root(n // 2, n) == complex(-1, 0)
+        assert oracle.root(3 * n // 4, n) == complex(0, 1)
+    w = np.array([oracle.root(k, 4096) for k in range(4096)])
+    assert np.max(np.abs(np.abs(w) - 1)) <= 2.3e-16
+    assert np.max(np.abs(w - np.exp(-2j * np.pi * np.arange(4096) / 4096))) < 1e-15
+
+
+@pytest.mark.parametrize("n", [1024, 4096])
+def test_gauss_sum_lfm_spectrum(n):
+    # h[m] = exp(i pi m^2 / N), N even: DFT = sqrt(N) e^{i pi/4} e^{-i pi k^2 / N}
+    m = np.arange(n)
+    h = np.exp(1j * np.pi * ((m * m) % (2 * n)) / n)
+    H = oracle.fft(h[None])[0]
+    k = np.arange(n)
+    expect = np.sqrt(n) * np.exp(1j * np.pi / 4) * np.exp(-1j * np.pi * ((k * k) % (2 * n)) / n)
+    assert np.max(np.abs(H - expect)) < 1e-9
+
+
+def test_matched_filter_normalised_and_peaks_at_delay():
+    n, L = 4096, 1024
+    h = scenes.range_replica_padded(n, L)
+    H = oracle.matched_filter(h, n)
+    assert abs(np.max(np.abs(H)) - 1.0) < 1e-15
+    ref = np.conj(np.fft.fft(h))
+    ref = ref / np.max(np.abs(ref))
+    assert np.max(np.abs(H - ref)) < 1e-12
+    for d in (0, 17, 3072):
+        x = np.zeros((1, n), complex)
+        x[0, d:d + L] = h[:L]
+        y = oracle.compress(x, H)[0]
+        assert int(np.argmax(np.abs(y))) == d
+        # peak = sum|h|^2 / max|DFT h| (matched gain)
+        assert abs(np.abs(y[d]) - L / np.max(np.abs(np.fft.fft(h)))) < 1e-9
+
+
+def test_compress_equals_circular_correlation():
+    # y = IDFT(DFT(x) conj(DFT(h))) / c is the circular cross-correlation / c
+    n = 64
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    h = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    H = oracle.matched_filter(h, n)
+    c = np.max(np.abs(np.fft.fft(h)))
+    y = oracle.compress(x[None], H)[0]
+    corr = np.array([np.sum(x * np.conj(np.roll(h, d))) for d in range(n)]) / c
+    assert np.max(np.abs(y - corr)) < 1e-12
+
+
+def test_zadoff_chu_overflow_mechanism():
+    # Sec. III-B: with |DFT x| = sqrt(N) flat and |H| = 1 the compressed output
+    # is sqrt(N) delta; the unscaled inverse peaks at N^1.5 > 65504.
+    n = 4096
+    m = np.arange(n)
+    x = np.exp(-1j * np.pi * ((m * m) % (2 * n)) / n)
+    X = oracle.fft(x[None])[0]
+    assert np.allclose(np.abs(X), np.sqrt(n), rtol=1e-12)
+    H = np.conj(X) / np.sqrt(n)
+    y = oracle.compress(x[None], H)[0]
+    expect = np.zeros(n, complex)
+    expect[0] = np.sqrt(n)
+    assert np.max(np.abs(y - expect)) < 1e-10
+    unscaled = oracle.fft(np.conj(X * H)[None])[0]
+    assert np.max(np.abs(unscaled)) == pytest.approx(n ** 1.5, rel=1e-12)
+    assert n ** 1.5 > 65504
+
+
+def test_transpose_and_sar_chain_composition():
+    rng = np.random.default_rng(9)
+    npul, nr = 32, 64
+    echo = rng.standard_normal((npul, nr)) + 1j * rng.standard_normal((npul, nr))
+    Hr = oracle.matched_filter(rng.standard_normal(nr) + 1j * rng.standard_normal(nr), nr)
+    Ha = oracle.matched_filter(rng.standard_normal(npul) + 1j * rng.standard_normal(npul), npul)
+    img, rct = oracle.sar_image(echo, Hr, Ha, return_rc=True)
+    # independent composition with numpy's FFT
+    rc = np.fft.ifft(np.fft.fft(echo, axis=1) * Hr[None], axis=1)
+    assert np.max(np.abs(rct - rc.T)) < 1e-12
+    ref = np.fft.ifft(np.fft.fft(rc.T, axis=1) * Ha[None], axis=1)
+    assert img.shape == (nr, npul)
+    assert np.max(np.abs(img - ref)) < 1e-12
+    phi = rng.uniform(-3, 3, npul)
+    img2 = oracle.sar_image(echo, Hr, Ha, phi=phi)
+    ref2 = np.fft.ifft(np.fft.fft(rc.T * np.exp(1j * phi)[None], axis=1) * Ha[None], axis=1)
+    assert np.max(np.abs(img2 - ref2)) < 1e-12
+
+
+def test_adjoint_identity():
+    # <A x, y> = <x, A^H y>, A^H = same chain with conj(H)
+    n = 256
+    rng = np.random.default_rng(2)
+    H = oracle.matched_filter(rng.standard_normal(n) + 1j * rng.standard_normal(n), n)
+    x = _rand(3, n, 4)
+    y = _rand(3, n, 5)
+    Ax = oracle.compress(x, H)
+    AHy = oracle.compress(y, H, conj_filter=True)
+    lhs = np.vdot(y, Ax)
+    rhs = np.vdot(AHy, x)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_entropy_definition_and_gradient():
+    rng = np.random.default_rng(8)
+    I = rng.standard_normal((4, 8)) + 1j * rng.standard_normal((4, 8))
+    I[0, 0] = 0.0  # 0 ln 0 = 0
+    E, G = oracle.entropy(I, want_grad=True)
+    p = np.abs(I) ** 2 / np.sum(np.abs(I) ** 2)
+    nz = p > 0
+    assert E == pytest.approx(-np.sum(p[nz] * np.log(p[nz])), rel=1e-14)
+    # uniform magnitudes give the maximum ln(count)
+    assert oracle.entropy(np.exp(1j * rng.uniform(0, 6, 32))) == pytest.approx(np.log(32), rel=1e-14)
+    # real-pair gradient vs central differences on Re and Im parts
+    h = 1e-6
+    for (i, j) in [(1, 2), (3, 7)]:
+        for unit in (1.0, 1j):
+            Ip = I.copy(); Ip[i, j] += h * unit
+            Im = I.copy(); Im[i, j] -= h * unit
+            fd = (oracle.entropy(Ip) - oracle.entropy(Im)) / (2 * h)
+            an = G[i, j].real if unit == 1.0 else G[i, j].imag
+            assert fd == pytest.approx(an, rel=1e-6, abs=1e-10)
+
+
+def test_autofocus_gradient_fd_and_invariance():
+    rng = np.random.default_rng(6)
+    nr, npul = 16, 64
+    rc = rng.standard_normal((nr, npul)) + 1j * rng.standard_normal((nr, npul))
+    Ha = oracle.matched_filter(scenes.azimuth_replica_centred(npul, 16), npul)
+    phi = rng.uniform(-1, 1, npul)
+    E, g = oracle.autofocus(rc, Ha, phi)
+    # constant-phase invariance: sum_m dE/dphi_m = 0
+    assert abs(np.sum(g)) <= 1e-10 * np.sum(np.abs(g))
+    h = 1e-4  # central differences: O(h^2) truncation, ~1e-11 roundoff
+    for m in (0, 5, 63):
+        pp = phi.copy(); pp[m] += h
+        pm = phi.copy(); pm[m] -= h
+        fd = (oracle.autofocus(rc, Ha, pp)[0] - oracle.autofocus(rc, Ha, pm)[0]) / (2 * h)
+        assert fd == pytest.approx(g[m], rel=1e-6, abs=1e-10)

@@ -1,0 +1,72 @@
+"""Seeded input generators and storage encoders (host only)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import emulator
+from paper_2605_28451_amd import scenes
+
+
+def _probe_values():
+    rng = np.random.default_rng(1)
+    v = np.concatenate([
+        rng.standard_normal(20000) * 10.0 ** rng.uniform(-6, 5, 20000),
+        [0.0, -0.0, 448.0, 449.0, 464.0, 480.0, 1e6, -1e6, 57344.0, 6e4, 2.0 ** -9, 2.0 ** -10,
+         3 * 2.0 ** -11, 2.0 ** -16, 2.0 ** -17, 3 * 2.0 ** -18, 0.0625 * 1.0625],
+    ])
+    return v
+
+
+@pytest.mark.parametrize("fmt,tdtype", [("e4m3", torch.float8_e4m3fn), ("e5m2", torch.float8_e5m2)])
+def test_fp8_encoder_matches_torch_and_emulator(fmt, tdtype):
+    v = _probe_values()
+    vmax = 448.0 if fmt == "e4m3" else 57344.0
+    enc = scenes.encode(v.astype(np.complex128), fmt)[..., 0]
+    # torch's cast is RNE without saturation: clamp first (library routine)
+    t = torch.from_numpy(np.clip(v, -vmax, vmax)).to(tdtype)
+    assert np.array_equal(enc, t.view(torch.uint8).numpy())
+    dec = scenes.decode(np.stack([enc, enc], -1), fmt).real
+    assert np.array_equal(dec, emulator.round_to_format(v, fmt))
+    assert np.array_equal(dec, t.to(torch.float64).numpy())
+
+
+def test_fp16_fp32_encoders_round_nearest_even():
+    v = _probe_values()
+    with np.errstate(over="ignore"):
+        assert np.array_equal(scenes.encode(v.astype(complex), "fp16")[..., 0], v.astype(np.float16))
+    assert np.array_equal(scenes.encode(v.astype(complex), "fp32")[..., 0], v.astype(np.float32))
+    x = v[:100] + 1j * v[100:200]
+    for fmt in ("fp16", "fp32", "e4m3", "e5m2"):
+        with np.errstate(over="ignore"):
+            e = scenes.encode(x, fmt)
+        assert e.shape == x.shape + (2,)
+        with np.errstate(over="ignore"):
+            q = scenes.quantize(x, fmt)
+        assert np.array_equal(q.real, scenes.decode(e, fmt).real)
+
+
+def test_chirp_exact_phase_reduction():
+    L = 1024
+    h = scenes.lfm_chirp(L)
+    n = np.arange(L) - L // 2
+    direct = np.exp(1j * np.pi * 0.8 * n.astype(float) ** 2 / L)
+    assert np.max(np.abs(h - direct)) < 1e-11
+    assert np.allclose(np.abs(h), 1.0, atol=1e-15)
+    g = scenes.azimuth_replica_centred(4096, 512)
+    assert np.count_nonzero(g) == 512 and g[0] == 1.0
+    assert np.allclose(g[1], np.exp(-1j * np.pi * 0.8 / 512))
+
+
+def test_scenes_are_seeded_and_shaped():
+    a = scenes.range_scene(seed=2, n_pulses=8)
+    b = scenes.range_scene(seed=2, n_pulses=8)
+    assert np.array_equal(a.echo, b.echo) and a.echo.shape == (8, 4096)
+    assert len(a.delays) == 5 and np.all(a.delays <= 4096 - 1024)
+    ub = scenes.uneven_batch(seed=4, count=100)
+    assert ub.x.size == int(np.sum(1 << ub.log2n.astype(np.int64)))
+    assert set(np.unique(ub.log2n)) <= set(range(8, 15)) and set(np.unique(ub.inverse)) <= {0, 1}
+    phi = scenes.autofocus_phase_error(n_pulse=4096)
+    # quadratic of 4 pi at +/-256 pulses around the centre (plus N(0, 0.3) jitter)
+    assert abs(phi[2048 + 256] - phi[2048] - 4 * np.pi) < 3.0
+    sc = scenes.sar_scene(seed=3, n=512, ranges=(100,), azimuths=(256,), length=64, aperture=32)
+    assert sc.echo.shape == (512, 512) and sc.targets == [(100, 256)]
