@@ -1,0 +1,224 @@
+/*
+ * bfpfft.h -- C ABI of the block-floating-point half-precision FFT and the
+ * range-Doppler SAR chain built on it, for AMD Instinct MI355X (gfx950).
+ *
+ * Method (arXiv 2605.28451, "Range, Not Precision"):
+ *   * matched-filter compression y = (1/N) IFFT(FFT(x) . H) with the inverse
+ *     realised as conj-FFT-conj (Sec. III-B);
+ *   * fixed-shift block floating point: the exact factor 1/N = 2^-log2(N) is
+ *     folded into the conjugate that precedes every inverse transform
+ *     (Eq. (1), Sec. IV-A), so every intermediate stays within O(N) and the
+ *     result equals the conventionally scaled inverse;
+ *   * the cascade of Sec. IV-B: range compression emits O(1) data, so the
+ *     azimuth FFT emits O(N) spectra and its own BFP inverse stays in range.
+ *
+ * Conventions shared by every entry point
+ *   - Data pointers are HIP device pointers owned by the caller.  Host
+ *     pointers are marked "(host)".  Streams are hipStream_t passed as void*
+ *     (NULL = the legacy default stream).
+ *   - Complex data is interleaved (re, im); rows are contiguous, row-major.
+ *     The element type follows the precision mode (bfp_storage_bytes).
+ *   - Execution calls are asynchronous on the given stream: they validate
+ *     their arguments, enqueue kernels and return.  Device faults surface at
+ *     the next synchronisation.  in == out is allowed for fft_exec_* (each
+ *     row is read completely before any of it is written).
+ *   - Every function returns BFP_OK (0) or a negative bfp_status; none
+ *     throws across the ABI.  bfp_last_error() returns a message for the
+ *     last failure on the calling thread.
+ *   - Plans are immutable after creation and may be used concurrently from
+ *     several streams; a plan's non-finite counter is shared by all of them.
+ */
+#ifndef BFPFFT_H
+#define BFPFFT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bfp_plan_s *bfp_plan;
+
+/* ------------------------------------------------------------ status --- */
+enum bfp_status {
+  BFP_OK = 0,
+  BFP_EINVAL = -1,        /* bad argument (size, pointer, mode, flag) */
+  BFP_EUNSUPPORTED = -2,  /* valid request this build does not implement */
+  BFP_ENOMEM = -3,        /* device or host allocation failed */
+  BFP_EHIP = -4,          /* a HIP runtime call failed (see bfp_last_error) */
+  BFP_ENODEV = -5         /* no gfx950 device visible */
+};
+
+/* ------------------------------------------------------ precision --- */
+/* Precision modes (paper Sec. V lists four; FP8 storage is Sec. VI).
+ * "storage" = HBM element type; on-chip (LDS) intermediates between radix
+ * passes are stored as noted; arithmetic as noted.                         */
+enum bfp_precision {
+  BFP_FP32 = 0,                    /* FP32 storage, LDS, twiddles, arithmetic  */
+  BFP_FP16 = 1,                    /* pure FP16: packed half2 arithmetic, FP16
+                                      twiddles, FP16 LDS and storage           */
+  BFP_FP16_STORE_FP32_COMPUTE = 2, /* FP16 storage and LDS, FP32 twiddles and
+                                      arithmetic                              */
+  BFP_FP16_MUL_FP32_ACC = 3,       /* FP16 storage, LDS and twiddles; every
+                                      twiddle/filter product takes FP16
+                                      operands and accumulates in FP32         */
+  BFP_FP8_E4M3_STORE = 4,          /* OCP FP8 E4M3 storage (saturating RNE),
+                                      FP32 LDS, twiddles and arithmetic        */
+  BFP_FP8_E5M2_STORE = 5           /* OCP FP8 E5M2 storage, otherwise as above */
+};
+
+/* Storage formats for bfp_convert and for tables. */
+enum bfp_format {
+  BFP_FMT_F32 = 0,   /* 8 bytes per complex  */
+  BFP_FMT_F16 = 1,   /* 4 bytes per complex  */
+  BFP_FMT_E4M3 = 2,  /* 2 bytes per complex  */
+  BFP_FMT_E5M2 = 3   /* 2 bytes per complex  */
+};
+
+/* ----------------------------------------------------------- flags --- */
+enum bfp_flags {
+  /* Debug: conventional output scaling instead of the BFP fold.  The
+   * unscaled inverse is rounded to the storage format first and multiplied
+   * by 2^-log2(N) afterwards, which overflows FP16 storage (Sec. III-B). */
+  BFP_FLAG_NAIVE_POSTSCALE = 1u,
+  /* Count non-finite output values into the plan's counter
+   * (read with fft_plan_nonfinite). */
+  BFP_FLAG_CHECK_FINITE = 2u,
+  /* Output stored as interleaved FP32 whatever the precision mode. */
+  BFP_FLAG_OUT_FP32 = 8u,
+  /* Use conj(filter): the adjoint of the compression chain. */
+  BFP_FLAG_CONJ_FILTER = 16u,
+  /* Plan flag: allocate the autofocus workspace (FP32 twiddles and the
+   * phase-gradient partial sums, up to 16 MiB at n = 16384). */
+  BFP_FLAG_AUTOFOCUS = 32u
+};
+
+/* Bytes per complex element in HBM for a precision mode (-1 if invalid). */
+int bfp_storage_bytes(int prec);
+/* Storage format of filters for a precision mode: BFP_FMT_F16 for the FP16
+ * modes, BFP_FMT_F32 for FP32 and the FP8-storage modes. */
+int bfp_filter_format(int prec);
+/* Bytes per complex element of a storage format (-1 if invalid). */
+int bfp_format_bytes(int fmt);
+
+const char *bfp_status_string(int status);
+const char *bfp_last_error(void);
+
+/* Number of visible gfx950 devices (0 when none).  Never fails. */
+int bfp_device_count(void);
+
+/* ------------------------------------------------------------ plans --- */
+/* Plan for `batch` independent transforms of length n = 2^k, 2^8..2^14, in
+ * precision mode `prec`.  flags: BFP_FLAG_CHECK_FINITE, BFP_FLAG_OUT_FP32.
+ * The plan owns its device twiddle tables (built on the host in FP64 with
+ * exact argument reduction and rounded once, never by recurrence: Sec.
+ * III-A) and its non-finite counter; it is bound to the device current at
+ * creation.  Errors: BFP_EINVAL (n not a supported power of two, batch < 0,
+ * bad mode), BFP_ENODEV, BFP_ENOMEM, BFP_EHIP. */
+int fft_plan(bfp_plan *out, int n, int batch, int prec, unsigned flags);
+int fft_destroy(bfp_plan p);
+/* Query: any output pointer may be NULL. */
+int fft_plan_info(bfp_plan p, int *n, int *batch, int *prec, unsigned *flags);
+
+/* X = DFT_N(x) per row, unscaled (exponent 0): X[k] = sum x[n] e^{-2 pi i nk/N}
+ * (Sec. III-B).  in/out: batch x n elements of the plan's storage type
+ * (BFP_FLAG_OUT_FP32: out is FP32 pairs). */
+int fft_exec_fwd(bfp_plan p, const void *in, void *out, void *stream);
+
+/* BFP inverse, Eq. (1): y = conj(DFT_N(conj(in . filter) . 2^-log2N)), i.e.
+ * the normalised IDFT of in . filter.  filter: n elements in
+ * bfp_filter_format(prec), shared by every row, or NULL for none.  The
+ * 2^-log2N multiply is exact for normal results and rounds to nearest-even
+ * into subnormals.  BFP_FLAG_NAIVE_POSTSCALE in the plan flags or in
+ * `flags` selects the conventional scaling instead. */
+int fft_exec_inv_bfp(bfp_plan p, const void *in, void *out, const void *filter,
+                     void *stream);
+int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *filter,
+                           unsigned flags, void *stream);
+
+/* Reads and clears the plan's non-finite counter; synchronises `stream`. */
+int fft_plan_nonfinite(bfp_plan p, void *stream, unsigned long long *count);
+
+/* -------------------------------------------------- uneven batches --- */
+/* One persistent launch over `count` transforms of mixed length
+ * (n_i = 2^log2n[i], 8 <= log2n[i] <= 14) and per-transform direction
+ * (inverse[i] = 0: forward; 1: BFP inverse without filter), packed back to
+ * back in the given order.  log2n and inverse are (host) arrays copied into
+ * the plan.  Work is split into equal-size tiles of 16384 complex elements
+ * (one transform of 16384, two of 8192, ..., 64 of 256) dispatched longest-
+ * first from a device work queue. */
+int fft_plan_uneven(bfp_plan *out, int count, const int *log2n,
+                    const unsigned char *inverse, int prec, unsigned flags);
+/* (host) offsets[count]: element offset of each transform in the packing. */
+int fft_uneven_offsets(bfp_plan p, long long *offsets);
+/* Total complex elements of the packed buffer. */
+int fft_uneven_total(bfp_plan p, long long *total);
+int fft_exec_uneven(bfp_plan p, const void *in, void *out, void *stream);
+
+/* ------------------------------------------------------------ tables --- */
+/* Matched filter for a replica (host) h[len] (interleaved FP64 pairs),
+ * zero-padded to n: H = conj(DFT_n(h)) / max_k |DFT_n(h)|, so |H| <= 1
+ * (Sec. III-B).  Computed on the host in FP64 and rounded once to `fmt`
+ * into (host) out_host[n]. */
+int bfp_make_filter(const double *h, int len, int n, int fmt, void *out_host);
+
+/* Element-wise storage conversion of `count` complex values on the device,
+ * rounding to nearest-even; FP8 targets saturate at their largest finite
+ * value (E4M3: 448, E5M2: 57344).  in != out. */
+int bfp_convert(const void *in, int in_fmt, void *out, int out_fmt, long long count,
+                void *stream);
+
+/* --------------------------------------------------------------- SAR --- */
+/* Fused range compression (Fig. 1, left group): per pulse row,
+ * rc = conj(DFT(conj(DFT(echo) . H_r) . 2^-log2N)), one HBM read and one
+ * write per row.  range_plan: n = range samples, its mode sets the storage
+ * type; n_pulses <= plan batch is the number of rows processed.  h_range:
+ * n elements in bfp_filter_format(prec).  flags: BFP_FLAG_NAIVE_POSTSCALE,
+ * BFP_FLAG_CONJ_FILTER, BFP_FLAG_OUT_FP32, BFP_FLAG_CHECK_FINITE. */
+int sar_range_compress(bfp_plan range_plan, const void *echo, void *rc, const void *h_range,
+                       int n_pulses, unsigned flags, void *stream);
+
+/* Corner turn: out[c][r] = in[r][c] for a rows x cols complex matrix in
+ * storage format `fmt`, staged through LDS tiles.  in != out. */
+int sar_corner_turn(const void *in, void *out, int rows, int cols, int fmt, void *stream);
+
+/* Fused azimuth compression (Fig. 1, right group) of range-compressed data
+ * laid out [range][pulse]: per range bin, the azimuth FFT, x H_a, the BFP
+ * fold and the inverse.  phase: NULL, or (device) n_az FP32 radians; when
+ * given, pulse m is first multiplied by exp(i phase[m]) (autofocus
+ * correction).  adjoint != 0 applies the adjoint chain (conj(H_a) and
+ * exp(-i phase[m]) applied after instead of before).  az_plan: n = pulses;
+ * n_range <= plan batch rows are processed.  The image is [range][azimuth]. */
+int sar_azimuth_compress(bfp_plan az_plan, const void *rc_t, void *image, const void *h_az,
+                         const float *phase, int n_range, int adjoint, unsigned flags,
+                         void *stream);
+
+/* ---------------------------------------------------------- autofocus --- */
+/* Entropy autofocus of the azimuth chain (gradient of the image entropy with
+ * respect to a per-pulse phase vector).  Images and image gradients are
+ * interleaved FP32 pairs.  stats is (device) 3 doubles: S = sum |I|^2,
+ * Q = sum |I|^2 ln |I|^2, E = ln S - Q / S = -sum p ln p with p = |I|^2 / S
+ * (0 ln 0 = 0).  The reductions run in a fixed order (deterministic). */
+int sar_image_entropy(bfp_plan plan, const void *image, long long count, double *stats,
+                      void *stream);
+
+/* grad = scale . dE/dI as a real pair (dE/dRe I + i dE/dIm I)
+ *      = scale . (-2/S)(ln p + E) I;  scale: (device) one float or NULL (1). */
+int sar_entropy_grad(const void *image, const double *stats, const float *scale, void *grad,
+                     long long count, void *stream);
+
+/* Gradient with respect to phase[m] of a real loss L of the image
+ * I = A_az(rc_t . exp(i phase)), given dL/dI as FP32 pairs in g (stats ==
+ * NULL), or, fused, given the image itself in g and its entropy stats
+ * (L = E).  Per range bin the adjoint chain A^H = IDFT diag(conj H_a) DFT is
+ * applied in FP32 and grad_phase[m] = sum_r Im(G_z[r][m] conj(z[r][m])) with
+ * z = rc_t . exp(i phase) (device, n_az floats out).  az_plan: precision
+ * BFP_FP32 or BFP_FP16_STORE_FP32_COMPUTE, created with BFP_FLAG_AUTOFOCUS;
+ * n_range <= plan batch.  Calls on one plan must not overlap (they share
+ * the plan's workspace). */
+int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, const double *stats,
+                           const void *h_az, const float *phase, float *grad_phase, int n_range,
+                           void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFPFFT_H */

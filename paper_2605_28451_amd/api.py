@@ -1,0 +1,263 @@
+"""Thin torch binding over the C ABI (argument marshalling only).
+
+Storage tensors carry a trailing axis of 2 (re, im): float32 for FP32,
+float16 for the FP16 modes, uint8 for the FP8 modes.  torch supplies device
+memory and the current stream; every step of the computation runs in the HIP
+kernels of libbfpfft.so.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (FILTER_OF, FLAG_CHECK_FINITE, FLAG_CONJ_FILTER, FLAG_NAIVE_POSTSCALE,
+                   FLAG_OUT_FP32, FORMATS, PRECISIONS, STORAGE_OF, check)
+
+TORCH_DTYPE = {"fp32": torch.float32, "fp16": torch.float16, "e4m3": torch.uint8, "e5m2": torch.uint8}
+
+
+def _prec(p):
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def storage_format(precision) -> str:
+    return STORAGE_OF[_prec(precision)]
+
+
+def filter_format(precision) -> str:
+    return FILTER_OF[_prec(precision)]
+
+
+def empty(shape, fmt: str, device="cuda"):
+    """Uninitialised storage tensor of complex shape `shape` in format `fmt`."""
+    return torch.empty(tuple(shape) + (2,), dtype=TORCH_DTYPE[fmt], device=device)
+
+
+def _check_storage(t, fmt, count, what):
+    if t.dtype != TORCH_DTYPE[fmt]:
+        raise TypeError(f"{what}: expected dtype {TORCH_DTYPE[fmt]} for {fmt}, got {t.dtype}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what}: must be a contiguous device tensor")
+    if t.numel() != 2 * count:
+        raise ValueError(f"{what}: expected {count} complex elements, got {t.numel() // 2}")
+
+
+def device_count() -> int:
+    return int(_lib.load().bfp_device_count())
+
+
+def make_filter(replica: np.ndarray, n: int, fmt: str) -> np.ndarray:
+    """Matched filter conj(DFT_n(h)) / max|DFT_n(h)| (host FP64, rounded once),
+    returned as a host storage array of shape (n, 2)."""
+    h = np.ascontiguousarray(np.asarray(replica, dtype=np.complex128).reshape(-1))
+    out = np.empty((n, 2), dtype={"fp32": np.float32, "fp16": np.float16,
+                                  "e4m3": np.uint8, "e5m2": np.uint8}[fmt])
+    check(_lib.load().bfp_make_filter(h.ctypes.data_as(ctypes.c_void_p), h.size, n,
+                                      FORMATS[fmt], out.ctypes.data_as(ctypes.c_void_p)),
+          "bfp_make_filter")
+    return out
+
+
+def filter_tensor(replica, n: int, precision, device="cuda"):
+    """The filter in the plan's filter format, on the device."""
+    return torch.from_numpy(make_filter(replica, n, filter_format(precision))).to(device)
+
+
+def convert(x, in_fmt: str, out_fmt: str, out=None, stream=None):
+    count = x.numel() // 2
+    _check_storage(x, in_fmt, count, "convert input")
+    if out is None:
+        out = torch.empty(x.shape, dtype=TORCH_DTYPE[out_fmt], device=x.device)
+    _check_storage(out, out_fmt, count, "convert output")
+    check(_lib.load().bfp_convert(_ptr(x), FORMATS[in_fmt], _ptr(out), FORMATS[out_fmt], count,
+                                  _stream(stream)), "bfp_convert")
+    return out
+
+
+def corner_turn(x, fmt: str, out=None, stream=None):
+    """out[c][r] = x[r][c] for a (rows, cols, 2) storage tensor."""
+    rows, cols = x.shape[0], x.shape[1]
+    _check_storage(x, fmt, rows * cols, "corner_turn input")
+    if out is None:
+        out = empty((cols, rows), fmt, x.device)
+    _check_storage(out, fmt, rows * cols, "corner_turn output")
+    check(_lib.load().sar_corner_turn(_ptr(x), _ptr(out), rows, cols, FORMATS[fmt],
+                                      _stream(stream)), "sar_corner_turn")
+    return out
+
+
+class FFTPlan:
+    """Batched length-n transforms in one precision mode (see include/bfpfft.h)."""
+
+    def __init__(self, n: int, batch: int, precision="fp16", flags: int = 0):
+        lib = _lib.load()
+        self.n = int(n)
+        self.batch = int(batch)
+        self.prec = _prec(precision)
+        self.flags = int(flags)
+        self._h = None
+        h = ctypes.c_void_p()
+        check(lib.fft_plan(ctypes.byref(h), self.n, self.batch, self.prec, self.flags), "fft_plan")
+        self._h = h
+        self.fmt = STORAGE_OF[self.prec]
+        self.filter_fmt = FILTER_OF[self.prec]
+
+    # ------------------------------------------------------------ helpers
+    def _out(self, out, rows, fp32=False):
+        fmt = "fp32" if fp32 else self.fmt
+        if out is None:
+            out = empty((rows, self.n), fmt)
+        _check_storage(out, fmt, rows * self.n, "output")
+        return out
+
+    def _rows_of(self, x, rows):
+        if rows is None:
+            rows = self.batch
+        _check_storage(x, self.fmt, rows * self.n, "input")
+        return rows
+
+    # -------------------------------------------------------------- calls
+    def forward(self, x, out=None, stream=None):
+        self._rows_of(x, None)
+        out = self._out(out, self.batch, bool(self.flags & FLAG_OUT_FP32))
+        check(_lib.load().fft_exec_fwd(self._h, _ptr(x), _ptr(out), _stream(stream)), "fft_exec_fwd")
+        return out
+
+    def inverse_bfp(self, z, filt=None, out=None, naive=False, conj_filter=False, stream=None):
+        self._rows_of(z, None)
+        out = self._out(out, self.batch, bool(self.flags & FLAG_OUT_FP32))
+        if filt is not None:
+            _check_storage(filt, self.filter_fmt, self.n, "filter")
+        fl = (FLAG_NAIVE_POSTSCALE if naive else 0) | (FLAG_CONJ_FILTER if conj_filter else 0)
+        check(_lib.load().fft_exec_inv_bfp_flags(self._h, _ptr(z), _ptr(out), _ptr(filt), fl,
+                                                 _stream(stream)), "fft_exec_inv_bfp")
+        return out
+
+    def range_compress(self, echo, filt, out=None, rows=None, naive=False, out_fp32=False,
+                       stream=None):
+        rows = self._rows_of(echo, rows)
+        out = self._out(out, rows, out_fp32 or bool(self.flags & FLAG_OUT_FP32))
+        _check_storage(filt, self.filter_fmt, self.n, "filter")
+        fl = (FLAG_NAIVE_POSTSCALE if naive else 0) | (FLAG_OUT_FP32 if out_fp32 else 0)
+        check(_lib.load().sar_range_compress(self._h, _ptr(echo), _ptr(out), _ptr(filt), rows, fl,
+                                             _stream(stream)), "sar_range_compress")
+        return out
+
+    def azimuth_compress(self, rc_t, filt, out=None, rows=None, phase=None, adjoint=False,
+                         naive=False, out_fp32=False, stream=None):
+        rows = self._rows_of(rc_t, rows)
+        out = self._out(out, rows, out_fp32 or bool(self.flags & FLAG_OUT_FP32))
+        _check_storage(filt, self.filter_fmt, self.n, "filter")
+        if phase is not None:
+            if phase.dtype != torch.float32 or phase.numel() != self.n or not phase.is_cuda:
+                raise ValueError("phase must be a float32 device tensor of n values")
+        fl = (FLAG_NAIVE_POSTSCALE if naive else 0) | (FLAG_OUT_FP32 if out_fp32 else 0)
+        check(_lib.load().sar_azimuth_compress(self._h, _ptr(rc_t), _ptr(out), _ptr(filt),
+                                               _ptr(phase), rows, int(bool(adjoint)), fl,
+                                               _stream(stream)), "sar_azimuth_compress")
+        return out
+
+    def nonfinite(self, stream=None) -> int:
+        c = ctypes.c_ulonglong()
+        check(_lib.load().fft_plan_nonfinite(self._h, _stream(stream), ctypes.byref(c)),
+              "fft_plan_nonfinite")
+        return int(c.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().fft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class UnevenPlan:
+    """One persistent launch over transforms of mixed length and direction.
+
+    log2n[i] in [8, 14]; inverse[i] = 1 selects the BFP inverse (no filter).
+    Transforms are packed back to back in the given order."""
+
+    def __init__(self, log2n, inverse, precision="fp16", flags: int = 0):
+        lib = _lib.load()
+        l2 = np.ascontiguousarray(np.asarray(log2n, dtype=np.int32))
+        inv = np.ascontiguousarray(np.asarray(inverse, dtype=np.uint8))
+        if l2.shape != inv.shape:
+            raise ValueError("log2n and inverse must have the same length")
+        self.count = int(l2.size)
+        self.prec = _prec(precision)
+        self._h = None
+        h = ctypes.c_void_p()
+        check(lib.fft_plan_uneven(ctypes.byref(h), self.count, l2.ctypes.data_as(ctypes.c_void_p),
+                                  inv.ctypes.data_as(ctypes.c_void_p), self.prec, int(flags)),
+              "fft_plan_uneven")
+        self._h = h
+        self.fmt = STORAGE_OF[self.prec]
+        tot = ctypes.c_longlong()
+        check(lib.fft_uneven_total(self._h, ctypes.byref(tot)), "fft_uneven_total")
+        self.total = int(tot.value)
+        self.offsets = np.empty(self.count, dtype=np.int64)
+        if self.count:
+            check(lib.fft_uneven_offsets(self._h, self.offsets.ctypes.data_as(
+                ctypes.POINTER(ctypes.c_longlong))), "fft_uneven_offsets")
+
+    def execute(self, x, out=None, stream=None):
+        _check_storage(x, self.fmt, self.total, "input")
+        if out is None:
+            out = empty((self.total,), self.fmt, x.device)
+        _check_storage(out, self.fmt, self.total, "output")
+        check(_lib.load().fft_exec_uneven(self._h, _ptr(x), _ptr(out), _stream(stream)),
+              "fft_exec_uneven")
+        return out
+
+    def nonfinite(self, stream=None) -> int:
+        c = ctypes.c_ulonglong()
+        check(_lib.load().fft_plan_nonfinite(self._h, _stream(stream), ctypes.byref(c)),
+              "fft_plan_nonfinite")
+        return int(c.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().fft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------- host helpers --
+def to_device(x: np.ndarray, fmt: str, device="cuda"):
+    """Encode complex values to `fmt` (round to nearest-even) and upload."""
+    from .scenes import encode
+    return torch.from_numpy(np.ascontiguousarray(encode(x, fmt))).to(device)
+
+
+def to_host(t, fmt: str) -> np.ndarray:
+    """Download a storage tensor and decode it exactly to complex128."""
+    from .scenes import decode
+    return decode(t.detach().cpu().numpy(), fmt)

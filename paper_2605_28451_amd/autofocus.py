@@ -1,0 +1,99 @@
+"""Entropy autofocus on the differentiable azimuth-compression chain.
+
+``AzimuthFocus`` and ``ImageEntropy`` are torch.autograd.Functions whose
+forward and backward passes are the HIP kernels of libbfpfft.so (the
+adjoint of the azimuth chain is the same block-floating-point chain with the
+conjugated filter).  ``entropy_and_grad`` is the fused path used in the
+optimisation loop: forward compression, entropy statistics, and the fused
+entropy-gradient + adjoint + per-pulse reduction, four kernel launches.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import FLAG_AUTOFOCUS, check
+from .api import FFTPlan, _check_storage, _ptr, _stream
+
+
+class AutofocusPlan(FFTPlan):
+    """Azimuth plan (n = pulses, batch = range bins) with the autofocus workspace."""
+
+    def __init__(self, n_az: int, n_range: int, precision="fp16_fp32", flags: int = 0):
+        super().__init__(n_az, n_range, precision, flags | FLAG_AUTOFOCUS)
+
+    def image(self, rc_t, h_az, phase, out=None, stream=None):
+        return self.azimuth_compress(rc_t, h_az, out=out, phase=phase, out_fp32=True, stream=stream)
+
+    def entropy_stats(self, img, stats=None, stream=None):
+        count = img.numel() // 2
+        _check_storage(img, "fp32", count, "image")
+        if stats is None:
+            stats = torch.empty(3, dtype=torch.float64, device=img.device)
+        check(_lib.load().sar_image_entropy(self._h, _ptr(img), count, _ptr(stats), _stream(stream)),
+              "sar_image_entropy")
+        return stats
+
+    def entropy_grad(self, img, stats, scale=None, out=None, stream=None):
+        count = img.numel() // 2
+        if out is None:
+            out = torch.empty_like(img)
+        check(_lib.load().sar_entropy_grad(_ptr(img), _ptr(stats), _ptr(scale), _ptr(out), count,
+                                           _stream(stream)), "sar_entropy_grad")
+        return out
+
+    def phase_grad(self, rc_t, g, h_az, phase, stats=None, out=None, stream=None):
+        """dL/dphase from dL/dI (stats None) or, fused, from the image and its
+        entropy stats (L = entropy)."""
+        rows = rc_t.numel() // (2 * self.n)
+        _check_storage(rc_t, self.fmt, rows * self.n, "rc_t")
+        _check_storage(g, "fp32", rows * self.n, "gradient/image")
+        _check_storage(h_az, self.filter_fmt, self.n, "filter")
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float32, device=rc_t.device)
+        check(_lib.load().sar_azimuth_phase_grad(self._h, _ptr(rc_t), _ptr(g), _ptr(stats),
+                                                 _ptr(h_az), _ptr(phase), _ptr(out), rows,
+                                                 _stream(stream)), "sar_azimuth_phase_grad")
+        return out
+
+
+class AzimuthFocus(torch.autograd.Function):
+    """I = A_az(rc_t . exp(i phase)) as FP32 pairs; gradient w.r.t. phase."""
+
+    @staticmethod
+    def forward(ctx, phase, plan, rc_t, h_az):
+        img = plan.image(rc_t, h_az, phase.detach().contiguous())
+        ctx.save_for_backward(phase)
+        ctx.plan, ctx.rc_t, ctx.h_az = plan, rc_t, h_az
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_img):
+        (phase,) = ctx.saved_tensors
+        g = ctx.plan.phase_grad(ctx.rc_t, grad_img.contiguous(), ctx.h_az, phase.detach().contiguous())
+        return g, None, None, None
+
+
+class ImageEntropy(torch.autograd.Function):
+    """E = -sum p ln p of an FP32-pair image; returns a 0-d float64 tensor."""
+
+    @staticmethod
+    def forward(ctx, img, plan):
+        stats = plan.entropy_stats(img)
+        ctx.save_for_backward(img, stats)
+        ctx.plan = plan
+        return stats[2].clone()
+
+    @staticmethod
+    def backward(ctx, gE):
+        img, stats = ctx.saved_tensors
+        scale = gE.detach().reshape(1).to(torch.float32).contiguous()
+        return ctx.plan.entropy_grad(img, stats, scale=scale), None
+
+
+def entropy_and_grad(plan, rc_t, h_az, phase, img=None, stats=None, grad=None):
+    """Fused path: (E as a device float64 scalar tensor, dE/dphase)."""
+    img = plan.image(rc_t, h_az, phase, out=img)
+    stats = plan.entropy_stats(img, stats)
+    grad = plan.phase_grad(rc_t, img, h_az, phase, stats=stats, out=grad)
+    return stats[2], grad, img

@@ -1,0 +1,436 @@
+// C ABI of libbfpfft: plans, argument validation, error reporting and the
+// host side of every entry point declared in include/bfpfft.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bfpfft.h"
+#include "host_tables.hpp"
+#include "internal.hpp"
+#include "plan.hpp"
+
+using bfp::RowArgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg) {
+  g_last_error = msg;
+  return status;
+}
+
+}  // namespace
+
+int bfp::set_error(int status, const std::string &msg) { return fail(status, msg); }
+
+namespace {
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(BFP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool valid_prec(int prec) { return prec >= BFP_FP32 && prec <= BFP_FP8_E5M2_STORE; }
+
+// twiddle table format of a mode
+int tw_format(int prec) {
+  return (prec == BFP_FP16 || prec == BFP_FP16_MUL_FP32_ACC) ? BFP_FMT_F16 : BFP_FMT_F32;
+}
+
+int log2_exact(long long n) {
+  if (n <= 0 || (n & (n - 1))) return -1;
+  int k = 0;
+  while ((1ll << k) < n) ++k;
+  return k;
+}
+
+}  // namespace
+
+namespace {
+
+int upload_twiddles(int log2n, int prec, void **out) {
+  int rad[4];
+  const int passes = bfp::pass_count(log2n);
+  for (int p = 0; p < 4; ++p) rad[p] = bfp::pass_radix(log2n, p);
+  std::vector<std::complex<double>> t = bfp::twiddle_table(log2n, rad, passes);
+  if ((int)t.size() != bfp::twiddle_entries(log2n))
+    return fail(BFP_EINVAL, "internal: twiddle table size mismatch");
+  const int fmt = tw_format(prec);
+  const size_t bytes = std::max<size_t>(16, t.size() * bfp_format_bytes(fmt));
+  std::vector<unsigned char> host(bytes, 0);
+  bfp::encode_complex(t.data(), t.size(), fmt, host.data());
+  void *d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return fail(BFP_ENOMEM, "hipMalloc twiddles failed");
+  e = hipMemcpy(d, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "hipMemcpy twiddles");
+  }
+  *out = d;
+  return BFP_OK;
+}
+
+int check_device() {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+    return fail(BFP_ENODEV, "no HIP device visible");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BFP_ENODEV, "hipGetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(BFP_ENODEV, "hipGetDeviceProperties failed");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(BFP_ENODEV, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+  return BFP_OK;
+}
+
+void free_plan(bfp_plan p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  (void)hipFree(p->tw);
+  (void)hipFree(p->nonfinite);
+  (void)hipFree(p->phasor);
+  (void)hipFree(p->items);
+  (void)hipFree(p->offsets_d);
+  (void)hipFree(p->inverse_d);
+  (void)hipFree(p->queue);
+  (void)hipFree(p->order_d);
+  if (p->tw32 != p->tw) (void)hipFree(p->tw32);
+  (void)hipFree(p->ent_partial);
+  (void)hipFree(p->pg_partial);
+  for (void *t : p->tw_sizes) (void)hipFree(t);
+  (void)hipFree(p->tw_ptrs_d);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+int check_rows_plan(bfp_plan p) {
+  if (!p) return fail(BFP_EINVAL, "plan is NULL");
+  if (p->kind != 0) return fail(BFP_EINVAL, "plan is not a batched-rows plan");
+  return BFP_OK;
+}
+
+unsigned kflags(unsigned f) {
+  unsigned k = 0;
+  if (f & BFP_FLAG_NAIVE_POSTSCALE) k |= bfp::KF_NAIVE;
+  if (f & BFP_FLAG_CHECK_FINITE) k |= bfp::KF_CHECK_FINITE;
+  if (f & BFP_FLAG_CONJ_FILTER) k |= bfp::KF_CONJ_FILTER;
+  return k;
+}
+
+int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
+             const void *phasor, int rows, unsigned flags, void *stream) {
+  if (rows < 0 || rows > p->batch) return fail(BFP_EINVAL, "row count outside [0, plan batch]");
+  if (rows == 0) return BFP_OK;
+  if (!in || !out) return fail(BFP_EINVAL, "NULL data pointer");
+  RowArgs a;
+  a.in = in;
+  a.out = out;
+  a.rows = rows;
+  a.tw = p->tw;
+  a.filter = filter;
+  a.phasor = phasor;
+  a.flags = kflags(flags | p->flags);
+  a.nonfinite = p->nonfinite;
+  const bool out32 = ((flags | p->flags) & BFP_FLAG_OUT_FP32) != 0;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) return fail(BFP_EINVAL, "plan belongs to another device");
+  hipError_t e = bfp::launch_rows(p->prec, p->log2n, op, out32, a, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BFP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bfp_storage_bytes(int prec) {
+  switch (prec) {
+    case BFP_FP32: return 8;
+    case BFP_FP16:
+    case BFP_FP16_STORE_FP32_COMPUTE:
+    case BFP_FP16_MUL_FP32_ACC: return 4;
+    case BFP_FP8_E4M3_STORE:
+    case BFP_FP8_E5M2_STORE: return 2;
+  }
+  return -1;
+}
+
+int bfp_filter_format(int prec) {
+  if (!valid_prec(prec)) return -1;
+  return (prec == BFP_FP16 || prec == BFP_FP16_STORE_FP32_COMPUTE || prec == BFP_FP16_MUL_FP32_ACC)
+             ? BFP_FMT_F16
+             : BFP_FMT_F32;
+}
+
+int bfp_format_bytes(int fmt) {
+  switch (fmt) {
+    case BFP_FMT_F32: return 8;
+    case BFP_FMT_F16: return 4;
+    case BFP_FMT_E4M3:
+    case BFP_FMT_E5M2: return 2;
+  }
+  return -1;
+}
+
+const char *bfp_status_string(int status) {
+  switch (status) {
+    case BFP_OK: return "ok";
+    case BFP_EINVAL: return "invalid argument";
+    case BFP_EUNSUPPORTED: return "unsupported";
+    case BFP_ENOMEM: return "out of memory";
+    case BFP_EHIP: return "HIP runtime error";
+    case BFP_ENODEV: return "no gfx950 device";
+  }
+  return "unknown status";
+}
+
+const char *bfp_last_error(void) { return g_last_error.c_str(); }
+
+int bfp_device_count(void) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return 0;
+  int n = 0;
+  for (int d = 0; d < count; ++d) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, d) == hipSuccess && strncmp(prop.gcnArchName, "gfx950", 6) == 0)
+      ++n;
+  }
+  return n;
+}
+
+int fft_plan(bfp_plan *out, int n, int batch, int prec, unsigned flags) {
+  if (!out) return fail(BFP_EINVAL, "out is NULL");
+  *out = nullptr;
+  const int l = log2_exact(n);
+  if (l < 8 || l > 14) return fail(BFP_EINVAL, "n must be a power of two in [256, 16384]");
+  if (batch < 0) return fail(BFP_EINVAL, "batch must be >= 0");
+  if (!valid_prec(prec)) return fail(BFP_EINVAL, "unknown precision mode");
+  if (flags & ~(unsigned)(BFP_FLAG_NAIVE_POSTSCALE | BFP_FLAG_CHECK_FINITE | BFP_FLAG_OUT_FP32 |
+                          BFP_FLAG_CONJ_FILTER | BFP_FLAG_AUTOFOCUS))
+    return fail(BFP_EINVAL, "unknown plan flag");
+  if ((flags & BFP_FLAG_AUTOFOCUS) && prec != BFP_FP32 && prec != BFP_FP16_STORE_FP32_COMPUTE)
+    return fail(BFP_EINVAL, "autofocus plans need BFP_FP32 or BFP_FP16_STORE_FP32_COMPUTE");
+  int st = check_device();
+  if (st) return st;
+  bfp_plan p = new (std::nothrow) bfp_plan_s;
+  if (!p) return fail(BFP_ENOMEM, "host allocation failed");
+  p->kind = 0;
+  p->n = n;
+  p->log2n = l;
+  p->batch = batch;
+  p->prec = prec;
+  p->flags = flags;
+  (void)hipGetDevice(&p->device);
+  st = upload_twiddles(l, prec, &p->tw);
+  if (st) {
+    free_plan(p);
+    return st;
+  }
+  if (hipMalloc((void **)&p->nonfinite, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&p->phasor, (size_t)n * 8) != hipSuccess) {
+    free_plan(p);
+    return fail(BFP_ENOMEM, "hipMalloc plan buffers failed");
+  }
+  hipError_t e = hipMemset(p->nonfinite, 0, sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "hipMemset");
+  }
+  if (hipMalloc((void **)&p->ent_partial, sizeof(double) * 2 * bfp::kEntropyBlocks) != hipSuccess) {
+    free_plan(p);
+    return fail(BFP_ENOMEM, "hipMalloc entropy workspace failed");
+  }
+  if (flags & BFP_FLAG_AUTOFOCUS) {
+    p->tw32 = p->tw;  // both admitted modes keep FP32 twiddles
+    const size_t bytes = sizeof(float) * (size_t)bfp::phase_grad_scratch_floats(l);
+    if (hipMalloc((void **)&p->pg_partial, bytes) != hipSuccess) {
+      free_plan(p);
+      return fail(BFP_ENOMEM, "hipMalloc autofocus workspace failed");
+    }
+  }
+  *out = p;
+  return BFP_OK;
+}
+
+int fft_destroy(bfp_plan p) {
+  if (!p) return fail(BFP_EINVAL, "plan is NULL");
+  free_plan(p);
+  return BFP_OK;
+}
+
+int fft_plan_info(bfp_plan p, int *n, int *batch, int *prec, unsigned *flags) {
+  if (!p) return fail(BFP_EINVAL, "plan is NULL");
+  if (n) *n = p->n;
+  if (batch) *batch = p->kind == 0 ? p->batch : p->count;
+  if (prec) *prec = p->prec;
+  if (flags) *flags = p->flags;
+  return BFP_OK;
+}
+
+int fft_exec_fwd(bfp_plan p, const void *in, void *out, void *stream) {
+  int st = check_rows_plan(p);
+  if (st) return st;
+  return run_rows(p, bfp::OP_FWD, in, out, nullptr, nullptr, p->batch, 0, stream);
+}
+
+int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *filter,
+                           unsigned flags, void *stream) {
+  int st = check_rows_plan(p);
+  if (st) return st;
+  if (flags & ~(unsigned)(BFP_FLAG_NAIVE_POSTSCALE | BFP_FLAG_CHECK_FINITE | BFP_FLAG_CONJ_FILTER))
+    return fail(BFP_EINVAL, "unknown flag for fft_exec_inv_bfp");
+  return run_rows(p, bfp::OP_INV, in, out, filter, nullptr, p->batch, flags, stream);
+}
+
+int fft_exec_inv_bfp(bfp_plan p, const void *in, void *out, const void *filter, void *stream) {
+  return fft_exec_inv_bfp_flags(p, in, out, filter, 0u, stream);
+}
+
+int fft_plan_nonfinite(bfp_plan p, void *stream, unsigned long long *count) {
+  if (!p || !count) return fail(BFP_EINVAL, "NULL argument");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  e = hipMemcpy(count, p->nonfinite, sizeof(unsigned long long), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy counter");
+  e = hipMemset(p->nonfinite, 0, sizeof(unsigned long long));
+  if (e != hipSuccess) return hip_fail(e, "hipMemset counter");
+  return BFP_OK;
+}
+
+int bfp_make_filter(const double *h, int len, int n, int fmt, void *out_host) {
+  if (!h || !out_host) return fail(BFP_EINVAL, "NULL argument");
+  if (log2_exact(n) < 0) return fail(BFP_EINVAL, "n must be a power of two");
+  if (len < 1 || len > n) return fail(BFP_EINVAL, "replica length must be in [1, n]");
+  if (bfp_format_bytes(fmt) < 0) return fail(BFP_EINVAL, "unknown format");
+  std::vector<std::complex<double>> a((size_t)n, std::complex<double>(0.0, 0.0));
+  for (int i = 0; i < len; ++i) a[i] = std::complex<double>(h[2 * i], h[2 * i + 1]);
+  bfp::host_fft(a);
+  double m = 0.0;
+  for (auto &v : a) m = std::max(m, std::abs(v));
+  if (!(m > 0.0)) return fail(BFP_EINVAL, "replica has an all-zero spectrum");
+  for (auto &v : a) v = std::conj(v) / m;
+  bfp::encode_complex(a.data(), a.size(), fmt, out_host);
+  return BFP_OK;
+}
+
+int bfp_convert(const void *in, int in_fmt, void *out, int out_fmt, long long count, void *stream) {
+  if (count < 0) return fail(BFP_EINVAL, "count < 0");
+  if (count == 0) return BFP_OK;
+  if (!in || !out) return fail(BFP_EINVAL, "NULL data pointer");
+  if (in == out) return fail(BFP_EINVAL, "in and out must differ");
+  if (bfp_format_bytes(in_fmt) < 0 || bfp_format_bytes(out_fmt) < 0)
+    return fail(BFP_EINVAL, "unknown format");
+  hipError_t e = bfp::launch_convert(in, in_fmt, out, out_fmt, count, (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "convert launch");
+}
+
+int sar_range_compress(bfp_plan range_plan, const void *echo, void *rc, const void *h_range,
+                       int n_pulses, unsigned flags, void *stream) {
+  int st = check_rows_plan(range_plan);
+  if (st) return st;
+  if (!h_range) return fail(BFP_EINVAL, "range filter is NULL");
+  if (flags & ~(unsigned)(BFP_FLAG_NAIVE_POSTSCALE | BFP_FLAG_CHECK_FINITE | BFP_FLAG_CONJ_FILTER |
+                          BFP_FLAG_OUT_FP32))
+    return fail(BFP_EINVAL, "unknown flag for sar_range_compress");
+  if (echo == rc) return fail(BFP_EINVAL, "echo and rc must differ");
+  return run_rows(range_plan, bfp::OP_COMPRESS, echo, rc, h_range, nullptr, n_pulses, flags,
+                  stream);
+}
+
+int sar_corner_turn(const void *in, void *out, int rows, int cols, int fmt, void *stream) {
+  if (rows < 0 || cols < 0) return fail(BFP_EINVAL, "negative size");
+  if (rows == 0 || cols == 0) return BFP_OK;
+  if (!in || !out) return fail(BFP_EINVAL, "NULL data pointer");
+  if (in == out) return fail(BFP_EINVAL, "in and out must differ");
+  const int b = bfp_format_bytes(fmt);
+  if (b < 0) return fail(BFP_EINVAL, "unknown format");
+  hipError_t e = bfp::launch_transpose(in, out, rows, cols, b, (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "corner turn launch");
+}
+
+int sar_azimuth_compress(bfp_plan az_plan, const void *rc_t, void *image, const void *h_az,
+                         const float *phase, int n_range, int adjoint, unsigned flags,
+                         void *stream) {
+  int st = check_rows_plan(az_plan);
+  if (st) return st;
+  if (!h_az) return fail(BFP_EINVAL, "azimuth filter is NULL");
+  if (flags & ~(unsigned)(BFP_FLAG_NAIVE_POSTSCALE | BFP_FLAG_CHECK_FINITE | BFP_FLAG_CONJ_FILTER |
+                          BFP_FLAG_OUT_FP32))
+    return fail(BFP_EINVAL, "unknown flag for sar_azimuth_compress");
+  if (rc_t == image) return fail(BFP_EINVAL, "rc_t and image must differ");
+  if (adjoint) {
+    if (phase) return fail(BFP_EUNSUPPORTED, "adjoint with phase: use the autofocus gradient");
+    flags ^= BFP_FLAG_CONJ_FILTER;
+  }
+  const void *ph = nullptr;
+  if (phase) {
+    hipError_t e = bfp::launch_phasor(phase, az_plan->phasor, az_plan->n, 0, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "phasor launch");
+    ph = az_plan->phasor;
+  }
+  return run_rows(az_plan, bfp::OP_COMPRESS, rc_t, image, h_az, ph, n_range, flags, stream);
+}
+
+int sar_image_entropy(bfp_plan plan, const void *image, long long count, double *stats,
+                      void *stream) {
+  if (!plan) return fail(BFP_EINVAL, "plan is NULL");
+  if (!plan->ent_partial) return fail(BFP_EINVAL, "plan has no entropy workspace");
+  if (count < 1) return fail(BFP_EINVAL, "count must be >= 1");
+  if (!image || !stats) return fail(BFP_EINVAL, "NULL pointer");
+  hipError_t e = bfp::launch_entropy(image, count, plan->ent_partial, stats, (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "entropy launch");
+}
+
+int sar_entropy_grad(const void *image, const double *stats, const float *scale, void *grad,
+                     long long count, void *stream) {
+  if (count < 0) return fail(BFP_EINVAL, "count < 0");
+  if (count == 0) return BFP_OK;
+  if (!image || !stats || !grad) return fail(BFP_EINVAL, "NULL pointer");
+  hipError_t e = bfp::launch_entropy_grad(image, stats, scale, grad, count, (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "entropy gradient launch");
+}
+
+int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, const double *stats,
+                           const void *h_az, const float *phase, float *grad_phase, int n_range,
+                           void *stream) {
+  int st = check_rows_plan(az_plan);
+  if (st) return st;
+  if (!az_plan->pg_partial) return fail(BFP_EINVAL, "plan was not created with BFP_FLAG_AUTOFOCUS");
+  if (n_range < 1 || n_range > az_plan->batch)
+    return fail(BFP_EINVAL, "n_range outside [1, plan batch]");
+  if (!rc_t || !g || !h_az || !phase || !grad_phase) return fail(BFP_EINVAL, "NULL pointer");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != az_plan->device) return fail(BFP_EINVAL, "plan belongs to another device");
+  hipError_t e = bfp::launch_phasor(phase, az_plan->phasor, az_plan->n, 0, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "phasor launch");
+  bfp::PhaseGradArgs a;
+  a.gimg = g;
+  a.stats = stats;
+  a.rc_t = rc_t;
+  a.filter = h_az;
+  a.phasor = az_plan->phasor;
+  a.tw32 = az_plan->tw32;
+  a.partial = az_plan->pg_partial;
+  a.grad = grad_phase;
+  a.rows = n_range;
+  e = bfp::launch_phase_grad(az_plan->prec == BFP_FP16_STORE_FP32_COMPUTE, az_plan->log2n, a,
+                             stats != nullptr, (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "phase gradient launch");
+}
+
+/* uneven entry points are defined in uneven_api.cpp */
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+// Differentiable azimuth compression for entropy autofocus.
+//
+// Forward (done by the row kernels): z[r][m] = rc_t[r][m] exp(i phi_m),
+// I = A(z) with A(v) = IDFT(DFT(v) . H_a) per range bin r.
+// Image entropy: E = -sum p ln p, p = |I|^2 / S, S = sum |I|^2; computed here
+// as E = ln S - Q / S with Q = sum |I|^2 ln |I|^2 (0 ln 0 = 0).
+// Gradient of a real loss L with respect to I as a real pair
+// (dL/dRe I + i dL/dIm I): for L = E it is G_I = -(2/S)(ln p + E) I.
+// Adjoint: A^H = IDFT . diag(conj H_a) . DFT (the same BFP chain with the
+// conjugated filter), so G_z = A^H(G_I), and since dz/dphi_m = i z,
+// dL/dphi_m = sum_r Im(G_z[r][m] conj(z[r][m])).
+//
+// phase_grad_kernel fuses, per range row: (optionally) forming G_I from the
+// image and the entropy statistics, the adjoint chain in FP32, the
+// re-formation of z from the FP16/FP32 range-compressed data and the phasor,
+// and the per-pulse accumulation of Im(G_z conj z).  Each workgroup
+// accumulates its rows in registers and writes one partial row; a second
+// kernel sums the partial rows in a fixed order (deterministic).
+#include "fft_engine.hpp"
+#include "internal.hpp"
+
+namespace bfp {
+
+// ------------------------------------------------------------- entropy ----
+constexpr int ENT_BLOCKS = 1024;
+
+__global__ void __launch_bounds__(256) entropy_partial_kernel(const c32 *__restrict__ img,
+                                                              long long count,
+                                                              double *__restrict__ partial) {
+  __shared__ double sh[2][256];
+  double s = 0.0, q = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const c32 v = img[i];
+    const double a = (double)v.x * v.x + (double)v.y * v.y;
+    s += a;
+    if (a > 0.0) q += a * log(a);
+  }
+  sh[0][threadIdx.x] = s;
+  sh[1][threadIdx.x] = q;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sh[0][0];
+    partial[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+__global__ void __launch_bounds__(256) entropy_final_kernel(const double *__restrict__ partial,
+                                                            int blocks, double *__restrict__ stats) {
+  __shared__ double sh[2][256];
+  double s = 0.0, q = 0.0;
+  for (int b = threadIdx.x; b < blocks; b += 256) {
+    s += partial[2 * b];
+    q += partial[2 * b + 1];
+  }
+  sh[0][threadIdx.x] = s;
+  sh[1][threadIdx.x] = q;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double S = sh[0][0], Q = sh[1][0];
+    stats[0] = S;
+    stats[1] = Q;
+    stats[2] = S > 0.0 ? log(S) - Q / S : 0.0;
+  }
+}
+
+hipError_t launch_entropy(const void *img, long long count, double *partial, double *stats,
+                          hipStream_t s) {
+  long long blocks = (count + 255) / 256;
+  if (blocks > ENT_BLOCKS) blocks = ENT_BLOCKS;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(entropy_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<const c32 *>(img), count, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(entropy_final_kernel, dim3(1), dim3(256), 0, s, partial, (int)blocks, stats);
+  return hipGetLastError();
+}
+
+// dE/dI scaled by an upstream factor: G = g (-2/S)(ln|I|^2 - ln S + E) I
+__device__ __forceinline__ c32 entropy_grad_of(c32 v, double S, double E, float g) {
+  const float a = v.x * v.x + v.y * v.y;
+  if (!(a > 0.0f)) return c32{0.0f, 0.0f};
+  const float c = (float)(-2.0 / S) * ((logf(a) - (float)log(S)) + (float)E) * g;
+  return c32{c * v.x, c * v.y};
+}
+
+__global__ void __launch_bounds__(256) entropy_grad_kernel(const c32 *__restrict__ img,
+                                                           const double *__restrict__ stats,
+                                                           const float *__restrict__ scale,
+                                                           c32 *__restrict__ grad, long long count) {
+  const double S = stats[0], E = stats[2];
+  const float g = scale ? scale[0] : 1.0f;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    grad[i] = entropy_grad_of(img[i], S, E, g);
+}
+
+hipError_t launch_entropy_grad(const void *img, const double *stats, const float *scale, void *grad,
+                               long long count, hipStream_t s) {
+  long long blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(entropy_grad_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<const c32 *>(img), stats, scale, static_cast<c32 *>(grad), count);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ phase gradient ----
+template <class S>
+__device__ __forceinline__ c32 load_any(const S *p, size_t i);
+template <>
+__device__ __forceinline__ c32 load_any<c32>(const c32 *p, size_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ c32 load_any<h2>(const h2 *p, size_t i) { return h2_to_c32(p[i]); }
+
+template <class StoreT, int LOG2N, bool FUSED>
+__global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGradArgs a) {
+  typedef Geometry<LOG2N> G;
+  typedef Engine<ModeFP32, LOG2N> EN;
+  constexpr int E = G::E, T = G::T, N = G::N;
+  constexpr float inv_n = 1.0f / (float)N;
+  __shared__ c32 lds_all[G::TPW * G::LDS_N];
+  const int local = threadIdx.x / T;
+  const int t = threadIdx.x & (T - 1);
+  c32 *lds = lds_all + local * G::LDS_N;
+  const c32 *tw = static_cast<const c32 *>(a.tw32);
+  const StoreT *flt = static_cast<const StoreT *>(a.filter);
+  const c32 *ph = static_cast<const c32 *>(a.phasor);
+  const c32 *gin = static_cast<const c32 *>(a.gimg);
+  const StoreT *rc = static_cast<const StoreT *>(a.rc_t);
+  double S = 0.0, Ent = 0.0;
+  if constexpr (FUSED) {
+    S = a.stats[0];
+    Ent = a.stats[2];
+  }
+  float acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+  const int groups = (a.rows + G::TPW - 1) / G::TPW;
+  for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+    const long long row = (long long)g * G::TPW + local;
+    const bool active = row < a.rows;
+    c32 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      c32 x = active ? gin[row * N + t + T * e] : c32{0.0f, 0.0f};
+      if constexpr (FUSED) x = entropy_grad_of(x, S, Ent, 1.0f);
+      v[e] = x;
+    }
+    EN::run(v, lds, tw, t);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const c32 h = load_any<StoreT>(flt, t + T * e);
+      v[e] = cscale(cconj(cmul(v[e], cconj(h))), inv_n);  // adjoint: conj(H_a)
+    }
+    EN::run(v, lds, tw, t);
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const c32 gz = cconj(v[e]);
+        const int m = t + T * e;
+        const c32 z = cmul(load_any<StoreT>(rc, row * N + m), ph[m]);
+        acc[e] += gz.y * z.x - gz.x * z.y;  // Im(gz conj z)
+      }
+    }
+  }
+  float *dst = a.partial + ((long long)blockIdx.x * G::TPW + local) * N;
+#pragma unroll
+  for (int e = 0; e < E; ++e) dst[t + T * e] = acc[e];
+}
+
+__global__ void __launch_bounds__(256) partial_sum_kernel(const float *__restrict__ partial, int parts,
+                                                          int n, float *__restrict__ out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double s = 0.0;
+  for (int p = 0; p < parts; ++p) s += partial[(long long)p * n + m];
+  out[m] = (float)s;
+}
+
+template <class StoreT, int LOG2N>
+static hipError_t launch_pg(const PhaseGradArgs &a, bool fused, int grid, hipStream_t s) {
+  typedef Geometry<LOG2N> G;
+  if (fused)
+    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, true>), dim3(grid), dim3(G::WG), 0, s, a);
+  else
+    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, false>), dim3(grid), dim3(G::WG), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n = G::N;
+  hipLaunchKernelGGL(partial_sum_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a.partial,
+                     grid * G::TPW, n, a.grad);
+  return hipGetLastError();
+}
+
+int phase_grad_grid(int log2n, int rows) {
+  const int T = threads_per_transform(log2n);
+  const int wg = T < 256 ? 256 : T;
+  const int tpw = wg / T;
+  int groups = (rows + tpw - 1) / tpw;
+  return groups < kPhaseGradBlocks ? (groups < 1 ? 1 : groups) : kPhaseGradBlocks;
+}
+
+long long phase_grad_scratch_floats(int log2n) {
+  const int T = threads_per_transform(log2n);
+  const int wg = T < 256 ? 256 : T;
+  return (long long)kPhaseGradBlocks * (wg / T) * (1ll << log2n);
+}
+
+hipError_t launch_phase_grad(bool fp16_storage, int log2n, const PhaseGradArgs &a, bool fused,
+                             hipStream_t s) {
+  const int grid = phase_grad_grid(log2n, a.rows);
+#define BFP_PG_CASE(L)                                                              \
+  case L:                                                                           \
+    return fp16_storage ? launch_pg<h2, L>(a, fused, grid, s) : launch_pg<c32, L>(a, fused, grid, s);
+  switch (log2n) {
+    BFP_PG_CASE(8)
+    BFP_PG_CASE(9)
+    BFP_PG_CASE(10)
+    BFP_PG_CASE(11)
+    BFP_PG_CASE(12)
+    BFP_PG_CASE(13)
+    BFP_PG_CASE(14)
+  }
+#undef BFP_PG_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace bfp

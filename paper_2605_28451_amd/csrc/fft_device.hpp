@@ -1,0 +1,331 @@
+// Device building blocks of the gfx950 FFT: complex arithmetic in FP32 and
+// packed FP16, constant-twiddle radix-2/4/8/16 DFTs, storage conversions
+// (FP32, FP16, OCP FP8 E4M3/E5M2) and the precision-mode policies.
+//
+// Everything here is device code compiled for gfx950 only.  No device code
+// evaluates a sine or cosine: twiddles come from host-built FP64 tables
+// rounded once (the paper, Sec. III-A, ties the poor "42 dB" FP16 folklore
+// to recurrence-built tables), and the few radix constants below are exact
+// decimal expansions rounded by the compiler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bfp {
+
+typedef _Float16 f16;
+typedef f16 h2 __attribute__((ext_vector_type(2)));  // (re, im) in one VGPR
+
+struct __attribute__((aligned(8))) c32 {
+  float x, y;
+};
+
+// ------------------------------------------------------------ FP32 ops ---
+__device__ __forceinline__ c32 mk(float x, float y) { return c32{x, y}; }
+__device__ __forceinline__ c32 cadd(c32 a, c32 b) { return c32{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c32 csub(c32 a, c32 b) { return c32{a.x - b.x, a.y - b.y}; }
+// a - i b and a + i b
+__device__ __forceinline__ c32 csub_i(c32 a, c32 b) { return c32{a.x + b.y, a.y - b.x}; }
+__device__ __forceinline__ c32 cadd_i(c32 a, c32 b) { return c32{a.x - b.y, a.y + b.x}; }
+__device__ __forceinline__ c32 cmul(c32 a, c32 b) {
+  return c32{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ c32 cscale(c32 a, float s) { return c32{a.x * s, a.y * s}; }
+__device__ __forceinline__ c32 cconj(c32 a) { return c32{a.x, -a.y}; }
+__device__ __forceinline__ c32 mul_mi(c32 a) { return c32{a.y, -a.x}; }   // x (-i)
+__device__ __forceinline__ c32 mul_pi(c32 a) { return c32{-a.y, a.x}; }   // x (+i)
+__device__ __forceinline__ c32 cneg(c32 a) { return c32{-a.x, -a.y}; }
+// x (c + i s) with compile-time constants
+__device__ __forceinline__ c32 cmulk(c32 a, float c, float s) {
+  return c32{a.x * c - a.y * s, a.x * s + a.y * c};
+}
+// x k (1 - i), x k (-1 - i), x k (-1 + i), x k (1 + i)
+__device__ __forceinline__ c32 mul_1mi(c32 a, float k) { return c32{(a.x + a.y) * k, (a.y - a.x) * k}; }
+__device__ __forceinline__ c32 mul_m1mi(c32 a, float k) { return c32{(a.y - a.x) * k, -(a.x + a.y) * k}; }
+__device__ __forceinline__ c32 mul_m1pi(c32 a, float k) { return c32{-(a.x + a.y) * k, (a.x - a.y) * k}; }
+__device__ __forceinline__ c32 mul_1pi(c32 a, float k) { return c32{(a.x - a.y) * k, (a.x + a.y) * k}; }
+
+// ----------------------------------------------------- packed FP16 ops ---
+__device__ __forceinline__ h2 cadd(h2 a, h2 b) { return a + b; }
+__device__ __forceinline__ h2 csub(h2 a, h2 b) { return a - b; }
+__device__ __forceinline__ h2 csub_i(h2 a, h2 b) { return a + h2{b.y, -b.x}; }
+__device__ __forceinline__ h2 cadd_i(h2 a, h2 b) { return a + h2{-b.y, b.x}; }
+__device__ __forceinline__ h2 cmul(h2 a, h2 b) {
+  h2 t = h2{a.x, a.x} * b;                 // (ax bx, ax by)
+  return h2{a.y, a.y} * h2{-b.y, b.x} + t; // + (-ay by, ay bx)
+}
+__device__ __forceinline__ h2 cscale(h2 a, float s) { return a * h2{(f16)s, (f16)s}; }
+__device__ __forceinline__ h2 cconj(h2 a) { return h2{a.x, -a.y}; }
+__device__ __forceinline__ h2 mul_mi(h2 a) { return h2{a.y, -a.x}; }
+__device__ __forceinline__ h2 mul_pi(h2 a) { return h2{-a.y, a.x}; }
+__device__ __forceinline__ h2 cneg(h2 a) { return -a; }
+__device__ __forceinline__ h2 cmulk(h2 a, float c, float s) {
+  return cmul(a, h2{(f16)c, (f16)s});
+}
+__device__ __forceinline__ h2 mul_1mi(h2 a, float k) { return (a + h2{a.y, -a.x}) * h2{(f16)k, (f16)k}; }
+__device__ __forceinline__ h2 mul_m1mi(h2 a, float k) { return (h2{a.y, -a.x} - a) * h2{(f16)k, (f16)k}; }
+__device__ __forceinline__ h2 mul_m1pi(h2 a, float k) { return (h2{-a.y, a.x} - a) * h2{(f16)k, (f16)k}; }
+__device__ __forceinline__ h2 mul_1pi(h2 a, float k) { return (a + h2{-a.y, a.x}) * h2{(f16)k, (f16)k}; }
+
+// ------------------------------------------------- radix constants ------
+// cos(pi/4), cos(pi/8), sin(pi/8) to 20 significant digits.
+#define BFP_C8 0.70710678118654752440f
+#define BFP_C16 0.92387953251128675613f
+#define BFP_S16 0.38268343236508977173f
+
+// a * W_R^e, W_R = exp(-2 pi i / R), e a compile-time constant
+template <int R, int E, class C>
+__device__ __forceinline__ C mulw(C a) {
+  constexpr int e = ((E % R) + R) % R;
+  if constexpr (e == 0) {
+    return a;
+  } else if constexpr (4 * e == R) {
+    return mul_mi(a);
+  } else if constexpr (2 * e == R) {
+    return cneg(a);
+  } else if constexpr (4 * e == 3 * R) {
+    return mul_pi(a);
+  } else if constexpr (8 * e == R) {
+    return mul_1mi(a, BFP_C8);       // e^{-i pi/4}
+  } else if constexpr (8 * e == 3 * R) {
+    return mul_m1mi(a, BFP_C8);      // e^{-3i pi/4}
+  } else if constexpr (8 * e == 5 * R) {
+    return mul_m1pi(a, BFP_C8);      // e^{-5i pi/4}
+  } else if constexpr (8 * e == 7 * R) {
+    return mul_1pi(a, BFP_C8);       // e^{-7i pi/4}
+  } else {
+    static_assert(R == 16, "generic constant twiddles only for radix 16");
+    // e odd: angle = 2 pi e / 16 = e pi / 8
+    constexpr int q = e;  // 1,3,5,7,9,11,13,15
+    constexpr float c = (q == 1 || q == 15) ? BFP_C16
+                      : (q == 3 || q == 13) ? BFP_S16
+                      : (q == 5 || q == 11) ? -BFP_S16
+                                            : -BFP_C16;  // 7, 9
+    constexpr float s = (q == 1 || q == 7) ? -BFP_S16
+                      : (q == 3 || q == 5) ? -BFP_C16
+                      : (q == 9 || q == 15) ? BFP_S16
+                                            : BFP_C16;   // 11, 13
+    return cmulk(a, c, s);
+  }
+}
+
+// ------------------------------------------------------------ DFTs ------
+// In-place length-R DFT (forward sign), natural order in and out.
+template <class C>
+__device__ __forceinline__ void dft2(C &a, C &b) {
+  C t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <class C>
+__device__ __forceinline__ void dft4(C &a, C &b, C &c, C &d) {
+  C s0 = cadd(a, c), s1 = csub(a, c), s2 = cadd(b, d), s3 = csub(b, d);
+  a = cadd(s0, s2);
+  c = csub(s0, s2);
+  b = csub_i(s1, s3);  // (a-c) - i(b-d)
+  d = cadd_i(s1, s3);  // (a-c) + i(b-d)
+}
+
+template <int R, class C>
+__device__ __forceinline__ void dft(C *v) {
+  if constexpr (R == 2) {
+    dft2(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    // n = n2 + 2 n1 (n2 < 2, n1 < 4), k = k1 + 4 k2
+    dft4(v[0], v[2], v[4], v[6]);  // n2 = 0 -> slots 0,2,4,6 hold k1 = 0..3
+    dft4(v[1], v[3], v[5], v[7]);  // n2 = 1
+    v[3] = mulw<8, 1>(v[3]);
+    v[5] = mulw<8, 2>(v[5]);
+    v[7] = mulw<8, 3>(v[7]);
+    C y[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      y[k1] = cadd(v[2 * k1], v[2 * k1 + 1]);
+      y[k1 + 4] = csub(v[2 * k1], v[2 * k1 + 1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = y[i];
+  } else if constexpr (R == 16) {
+    // n = n2 + 4 n1, k = k1 + 4 k2: DFT4 over n1, twiddle W16^{n2 k1},
+    // DFT4 over n2.
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+    // slot n2 + 4 k1 now holds Y[n2][k1]
+    v[5] = mulw<16, 1>(v[5]);
+    v[6] = mulw<16, 2>(v[6]);
+    v[7] = mulw<16, 3>(v[7]);
+    v[9] = mulw<16, 2>(v[9]);
+    v[10] = mulw<16, 4>(v[10]);
+    v[11] = mulw<16, 6>(v[11]);
+    v[13] = mulw<16, 3>(v[13]);
+    v[14] = mulw<16, 6>(v[14]);
+    v[15] = mulw<16, 9>(v[15]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // slot k2 + 4 k1 holds X[k1 + 4 k2]: transpose the 4x4 slot grid
+    C y[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) y[k1 + 4 * k2] = v[k2 + 4 * k1];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = y[i];
+  } else {
+    static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");
+  }
+}
+
+// ----------------------------------------------------- storage types ----
+struct __attribute__((aligned(2))) fp8x2 {
+  uint8_t x, y;
+};
+
+// OCP FP8 decode (exact).  E4M3: bias 7, 3 mantissa bits, 0x7F/0xFF NaN.
+// E5M2: bias 15, 2 mantissa bits, exponent 31 = inf/NaN.
+template <int MANT, int BIAS>
+__device__ __forceinline__ float fp8_decode(uint32_t b) {
+  uint32_t s = (b & 0x80u) << 24;
+  uint32_t e = (b >> MANT) & ((1u << (7 - MANT)) - 1u);
+  uint32_t m = b & ((1u << MANT) - 1u);
+  float v;
+  if (e == 0) {
+    v = (float)m * __builtin_bit_cast(float, (uint32_t)(127 + 1 - BIAS - MANT) << 23);
+  } else if (MANT == 3 && e == 15 && m == 7) {
+    v = __builtin_nanf("");
+  } else if (MANT == 2 && e == 31) {
+    v = m ? __builtin_nanf("") : __builtin_inff();
+  } else {
+    v = __builtin_bit_cast(float, ((e - BIAS + 127) << 23) | (m << (23 - MANT)));
+  }
+  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) | s);
+}
+
+// FP32 -> OCP FP8, round to nearest-even, saturating at the largest finite
+// value (NaN stays NaN).
+template <int MANT, int BIAS>
+__device__ __forceinline__ uint32_t fp8_encode(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  uint32_t s = (u >> 24) & 0x80u;
+  float a = __builtin_fabsf(x);
+  constexpr uint32_t emax_field = (MANT == 3) ? 15u : 30u;
+  constexpr uint32_t mmax = (MANT == 3) ? 6u : 3u;
+  // largest finite value: (1 + mmax / 2^MANT) * 2^(emax_field - BIAS)
+  const float maxv = __builtin_bit_cast(float, ((emax_field - BIAS + 127) << 23) | (mmax << (23 - MANT)));
+  if (!(a == a)) return s | 0x7Fu;  // NaN
+  if (a >= maxv) return s | (emax_field << MANT) | mmax;
+  const float min_normal = __builtin_bit_cast(float, (uint32_t)(127 + 1 - BIAS) << 23);
+  if (a < min_normal) {
+    // subnormal: multiple of 2^(1 - BIAS - MANT)
+    float q = __builtin_rintf(a * __builtin_bit_cast(float, (uint32_t)(127 - (1 - BIAS - MANT)) << 23));
+    return s | (uint32_t)q;  // q == 2^MANT rolls into the smallest normal
+  }
+  uint32_t ua = __builtin_bit_cast(uint32_t, a);
+  constexpr int drop = 23 - MANT;
+  ua += ((1u << (drop - 1)) - 1u) + ((ua >> drop) & 1u);
+  ua &= ~((1u << drop) - 1u);
+  uint32_t e = (ua >> 23) - 127 + BIAS;
+  uint32_t m = (ua >> drop) & ((1u << MANT) - 1u);
+  uint32_t r = (e << MANT) | m;
+  uint32_t rmax = (emax_field << MANT) | mmax;
+  return s | (r > rmax ? rmax : r);
+}
+
+// --------------------------------------------------- precision policies --
+// Each mode defines:
+//   Store: HBM element; Lds: on-chip element between passes;
+//   Comp: register arithmetic type; Tw: twiddle table element;
+//   Filt: filter element.
+// and the conversions/multiplies the engine needs.
+
+struct ModeFP32 {
+  typedef c32 Store; typedef c32 Lds; typedef c32 Comp; typedef c32 Tw; typedef c32 Filt;
+  static __device__ __forceinline__ Comp load(const Store *p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) { p[i] = v; }
+  static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
+  static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }
+  static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(v, w); }
+  static __device__ __forceinline__ Comp fmul(Comp v, Filt h) { return cmul(v, h); }
+  static __device__ __forceinline__ Comp round_store(Comp v) { return v; }
+};
+
+struct ModeFP16 {  // pure packed FP16
+  typedef h2 Store; typedef h2 Lds; typedef h2 Comp; typedef h2 Tw; typedef h2 Filt;
+  static __device__ __forceinline__ Comp load(const Store *p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) { p[i] = v; }
+  static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
+  static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }
+  static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(v, w); }
+  static __device__ __forceinline__ Comp fmul(Comp v, Filt h) { return cmul(v, h); }
+  static __device__ __forceinline__ Comp round_store(Comp v) { return v; }
+};
+
+__device__ __forceinline__ c32 h2_to_c32(h2 v) { return c32{(float)v.x, (float)v.y}; }
+__device__ __forceinline__ h2 c32_to_h2(c32 v) { return h2{(f16)v.x, (f16)v.y}; }
+
+struct ModeF16StoreF32 {
+  typedef h2 Store; typedef h2 Lds; typedef c32 Comp; typedef c32 Tw; typedef h2 Filt;
+  static __device__ __forceinline__ Comp load(const Store *p, size_t i) { return h2_to_c32(p[i]); }
+  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) { p[i] = c32_to_h2(v); }
+  static __device__ __forceinline__ Lds to_lds(Comp v) { return c32_to_h2(v); }
+  static __device__ __forceinline__ Comp from_lds(Lds v) { return h2_to_c32(v); }
+  static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(h2_to_c32(v), w); }
+  static __device__ __forceinline__ Comp fmul(Comp v, Filt h) { return cmul(v, h2_to_c32(h)); }
+  static __device__ __forceinline__ Comp round_store(Comp v) { return h2_to_c32(c32_to_h2(v)); }
+};
+
+// FP16 operands, FP32 accumulation: (a.x, a.y) . (b.x, -b.y) and
+// (a.x, a.y) . (b.y, b.x) with v_dot2_f32_f16.
+__device__ __forceinline__ c32 cmul_dot2(h2 a, h2 b) {
+  float re = __builtin_amdgcn_fdot2(a, h2{b.x, -b.y}, 0.0f, false);
+  float im = __builtin_amdgcn_fdot2(a, h2{b.y, b.x}, 0.0f, false);
+  return c32{re, im};
+}
+
+struct ModeF16MulF32Acc {
+  typedef h2 Store; typedef h2 Lds; typedef c32 Comp; typedef h2 Tw; typedef h2 Filt;
+  static __device__ __forceinline__ Comp load(const Store *p, size_t i) { return h2_to_c32(p[i]); }
+  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) { p[i] = c32_to_h2(v); }
+  static __device__ __forceinline__ Lds to_lds(Comp v) { return c32_to_h2(v); }
+  static __device__ __forceinline__ Comp from_lds(Lds v) { return h2_to_c32(v); }
+  static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul_dot2(v, w); }
+  static __device__ __forceinline__ Comp fmul(Comp v, Filt h) { return cmul_dot2(c32_to_h2(v), h); }
+  static __device__ __forceinline__ Comp round_store(Comp v) { return h2_to_c32(c32_to_h2(v)); }
+};
+
+template <int MANT, int BIAS>
+struct ModeFP8 {
+  typedef fp8x2 Store; typedef c32 Lds; typedef c32 Comp; typedef c32 Tw; typedef c32 Filt;
+  static __device__ __forceinline__ Comp load(const Store *p, size_t i) {
+    fp8x2 b = p[i];
+    return c32{fp8_decode<MANT, BIAS>(b.x), fp8_decode<MANT, BIAS>(b.y)};
+  }
+  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) {
+    p[i] = fp8x2{(uint8_t)fp8_encode<MANT, BIAS>(v.x), (uint8_t)fp8_encode<MANT, BIAS>(v.y)};
+  }
+  static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
+  static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }
+  static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(v, w); }
+  static __device__ __forceinline__ Comp fmul(Comp v, Filt h) { return cmul(v, h); }
+  static __device__ __forceinline__ Comp round_store(Comp v) {
+    return c32{fp8_decode<MANT, BIAS>(fp8_encode<MANT, BIAS>(v.x)),
+               fp8_decode<MANT, BIAS>(fp8_encode<MANT, BIAS>(v.y))};
+  }
+};
+typedef ModeFP8<3, 7> ModeE4M3;
+typedef ModeFP8<2, 15> ModeE5M2;
+
+__device__ __forceinline__ c32 to_c32(c32 v) { return v; }
+__device__ __forceinline__ c32 to_c32(h2 v) { return h2_to_c32(v); }
+
+__device__ __forceinline__ bool finite_c(c32 v) {
+  return __builtin_isfinite(v.x) && __builtin_isfinite(v.y);
+}
+__device__ __forceinline__ bool finite_c(h2 v) {
+  return __builtin_isfinite((float)v.x) && __builtin_isfinite((float)v.y);
+}
+
+}  // namespace bfp

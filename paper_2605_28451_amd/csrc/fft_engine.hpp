@@ -1,0 +1,151 @@
+// Single-pass, LDS-resident Stockham FFT engine for gfx950.
+//
+// One transform of N = 2^LOG2N points is processed by T = N / E threads that
+// each hold E complex values in registers.  N is factored into radix passes
+// (16 x 16 x 16 for N = 4096).  Pass p with radix R and span NS (the length of
+// the sub-transforms already combined) applies, to each of the N / R
+// butterflies j, the twiddles W_{NS R}^{(j mod NS) r} (r = 1..R-1), a
+// constant-twiddle DFT_R in registers, and writes the R results to positions
+// (j / NS) NS R + (j mod NS) + r NS of the LDS buffer: the self-sorting
+// (Stockham) order, so the final pass leaves X[k] in natural order.  Every
+// pass reads thread t's inputs from positions t + T e (e = 0..E-1), so the
+// first pass reads HBM and the last pass writes HBM with unit stride across
+// the threads of a wavefront (coalesced), and only the interior passes touch
+// LDS.  The LDS index is padded by one element per 16 to keep the scattered
+// Stockham writes free of bank conflicts.
+//
+// Twiddles come from a per-plan table in HBM (L2/L1-resident after the first
+// wavefronts): pass p owns NS_p x R_p entries W_{NS R}^{m r}, m < NS, r < R,
+// built on the host in FP64 and rounded once to the mode's twiddle type.
+#pragma once
+
+#include "fft_device.hpp"
+
+namespace bfp {
+
+// Radix plan per size: E values per thread, up to 4 passes.
+template <int LOG2N> struct Shape;
+template <> struct Shape<8>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 16, R2 = 1, R3 = 1; };
+template <> struct Shape<9>  { static constexpr int E = 8,  P = 3, R0 = 8,  R1 = 8,  R2 = 8, R3 = 1; };
+template <> struct Shape<10> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 4, R3 = 1; };
+template <> struct Shape<11> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 8, R3 = 1; };
+template <> struct Shape<12> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 16, R3 = 1; };
+template <> struct Shape<13> { static constexpr int E = 16, P = 4, R0 = 16, R1 = 16, R2 = 16, R3 = 2; };
+template <> struct Shape<14> { static constexpr int E = 16, P = 4, R0 = 16, R1 = 16, R2 = 16, R3 = 4; };
+
+template <int LOG2N>
+struct Geometry {
+  typedef Shape<LOG2N> S;
+  static constexpr int N = 1 << LOG2N;
+  static constexpr int E = S::E;
+  static constexpr int T = N / E;                    // threads per transform
+  static constexpr int WG = T < 256 ? 256 : T;       // threads per workgroup
+  static constexpr int TPW = WG / T;                 // transforms per workgroup
+  static constexpr int LDS_N = N + N / 16;           // padded LDS elements
+  static constexpr int radix(int p) {
+    return p == 0 ? S::R0 : p == 1 ? S::R1 : p == 2 ? S::R2 : S::R3;
+  }
+  static constexpr int span(int p) {  // NS of pass p
+    int ns = 1;
+    for (int q = 0; q < p; ++q) ns *= radix(q);
+    return ns;
+  }
+  // offset of pass p's twiddle block in the plan table (passes with NS > 1)
+  static constexpr int tw_offset(int p) {
+    int off = 0;
+    for (int q = 1; q < p; ++q) off += span(q) * radix(q);
+    return off;
+  }
+  static constexpr int tw_entries() { return tw_offset(S::P); }
+};
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+template <class M, int LOG2N>
+struct Engine {
+  typedef Geometry<LOG2N> G;
+  typedef typename M::Comp Comp;
+  typedef typename M::Lds Lds;
+  typedef typename M::Tw Tw;
+  static constexpr int E = G::E;
+  static constexpr int T = G::T;
+
+  template <int R>
+  static __device__ __forceinline__ void load_tw_row(const Tw *__restrict__ p, Tw (&w)[R]) {
+    static_assert((R * sizeof(Tw)) % 8 == 0, "twiddle row size");
+    if constexpr ((R * sizeof(Tw)) % 16 == 0) {
+      const uint4 *q = reinterpret_cast<const uint4 *>(p);
+      constexpr int nv = R * sizeof(Tw) / 16;
+      uint4 tmp[nv];
+#pragma unroll
+      for (int i = 0; i < nv; ++i) tmp[i] = q[i];
+      __builtin_memcpy(&w[0], &tmp[0], sizeof(tmp));
+    } else {
+      const uint2 *q = reinterpret_cast<const uint2 *>(p);
+      constexpr int nv = R * sizeof(Tw) / 8;
+      uint2 tmp[nv];
+#pragma unroll
+      for (int i = 0; i < nv; ++i) tmp[i] = q[i];
+      __builtin_memcpy(&w[0], &tmp[0], sizeof(tmp));
+    }
+  }
+
+  // One Stockham pass.  On entry v[e] holds this thread's inputs (pass 0)
+  // or nothing (later passes, which read LDS); on exit v[e] holds the
+  // outputs (last pass) or the outputs have been written to LDS.
+  template <int PASS>
+  static __device__ __forceinline__ void pass(Comp (&v)[E], Lds *lds, const Tw *__restrict__ tw,
+                                              int t) {
+    constexpr int R = G::radix(PASS);
+    constexpr int NS = G::span(PASS);
+    constexpr int B = E / R;
+    constexpr bool LAST = (PASS == G::S::P - 1);
+    if constexpr (PASS > 0) {
+      Lds raw[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) raw[e] = lds[lds_pad(t + T * e)];
+      const Tw *twp = tw + G::tw_offset(PASS);
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int j = t + T * b;
+        const int m = j & (NS - 1);
+        Tw w[R];
+        load_tw_row<R>(twp + m * R, w);
+        v[b] = M::from_lds(raw[b]);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[b + B * r] = M::twiddle(raw[b + B * r], w[r]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      Comp u[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[r] = v[b + B * r];
+      dft<R>(u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + B * r] = u[r];
+    }
+    if constexpr (!LAST) {
+      __syncthreads();  // all reads of the previous contents are done
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int j = t + T * b;
+        const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = M::to_lds(v[b + B * r]);
+      }
+      __syncthreads();
+    }
+  }
+
+  // Full forward transform: v[e] = x[t + T e] in, v[e] = X[t + T e] out.
+  static __device__ __forceinline__ void run(Comp (&v)[E], Lds *lds, const Tw *__restrict__ tw,
+                                             int t) {
+    pass<0>(v, lds, tw, t);
+    if constexpr (G::S::P > 1) pass<1>(v, lds, tw, t);
+    if constexpr (G::S::P > 2) pass<2>(v, lds, tw, t);
+    if constexpr (G::S::P > 3) pass<3>(v, lds, tw, t);
+  }
+};
+
+}  // namespace bfp

@@ -1,0 +1,19 @@
+// Host FP64 table builders (twiddles, matched filters) and storage encoders.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <complex>
+#include <vector>
+
+namespace bfp {
+
+std::complex<double> unit_root(long long k, long long n);
+uint16_t f64_to_f16_bits(double x);
+uint8_t f64_to_fp8_bits(double x, int mant, int bias);
+void encode_complex(const std::complex<double> *src, size_t count, int fmt, void *dst);
+std::vector<std::complex<double>> twiddle_table(int log2n, const int *radix, int passes);
+void host_fft(std::vector<std::complex<double>> &a);
+
+}  // namespace bfp

@@ -1,0 +1,95 @@
+// Host-side internal interfaces shared by the C-ABI layer and the kernel
+// translation units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bfp {
+
+enum Op { OP_FWD = 0, OP_INV = 1, OP_COMPRESS = 2 };
+
+// runtime flags understood by the row kernels
+enum KFlags : unsigned {
+  KF_NAIVE = 1u,         // conventional post-scaling instead of the BFP fold
+  KF_CHECK_FINITE = 2u,  // count non-finite outputs
+  KF_CONJ_FILTER = 16u,  // multiply by conj(filter)
+};
+
+struct RowArgs {
+  const void *in;
+  void *out;
+  int rows;
+  const void *tw;        // plan twiddle table (mode's twiddle type)
+  const void *filter;    // n elements or NULL
+  const void *phasor;    // n FP32 pairs exp(i phi_m) or NULL (compress only)
+  unsigned flags;        // KFlags
+  unsigned long long *nonfinite;  // device counter
+};
+
+// Launch a row kernel; returns hipSuccess or the launch error.
+hipError_t launch_rows(int mode, int log2n, int op, bool out32, const RowArgs &a,
+                       hipStream_t stream);
+
+// Number of twiddle-table entries of a size (all passes), and the
+// (pass span, radix) sequence used to fill it on the host.
+int twiddle_entries(int log2n);
+int pass_count(int log2n);
+int pass_radix(int log2n, int p);
+
+// Uneven persistent batch.
+struct UnevenArgs {
+  const void *in;
+  void *out;
+  const int4 *items;          // (first position in order[], count, log2n, 0) per item
+  const int *order;           // transform indices grouped by length, longest first
+  const long long *offsets;   // element offset of each transform
+  const unsigned char *inverse;
+  int n_items;
+  unsigned *queue;            // work counter, zeroed by the launcher's reset kernel
+  const void *const *tw;      // per-size twiddle tables, index log2n - 8
+  unsigned flags;
+  unsigned long long *nonfinite;
+};
+hipError_t launch_uneven(int mode, const UnevenArgs &a, int grid, hipStream_t stream);
+int uneven_blocks_per_cu(int mode);
+int threads_per_transform(int log2n);
+constexpr int kUnevenWG = 1024;
+
+// Element-wise storage conversion.
+hipError_t launch_convert(const void *in, int in_fmt, void *out, int out_fmt, long long count,
+                          hipStream_t stream);
+
+// Corner turn (transpose) of a rows x cols matrix of elements of `bytes`.
+hipError_t launch_transpose(const void *in, void *out, int rows, int cols, int bytes,
+                            hipStream_t stream);
+
+// exp(i phi) table (FP32 pairs) from FP32 radians.
+hipError_t launch_phasor(const float *phase, void *phasor, int n, int negate,
+                         hipStream_t stream);
+
+// Autofocus: entropy statistics (S, Q, E), entropy gradient and the fused
+// adjoint + per-pulse phase-gradient reduction.
+constexpr int kEntropyBlocks = 1024;
+constexpr int kPhaseGradBlocks = 256;
+struct PhaseGradArgs {
+  const void *gimg;      // FP32 pairs: dL/dI, or the image itself when fused
+  const double *stats;   // (S, Q, E) when fused, else unused
+  const void *rc_t;      // range-compressed data, plan storage (FP16 or FP32)
+  const void *filter;    // azimuth filter, plan filter format
+  const void *phasor;    // FP32 pairs exp(i phi_m)
+  const void *tw32;      // FP32 twiddle table of the size
+  float *partial;        // kPhaseGradBlocks * transforms-per-workgroup rows of n floats
+  float *grad;           // n floats out
+  int rows;
+};
+hipError_t launch_entropy(const void *img, long long count, double *partial, double *stats,
+                          hipStream_t s);
+hipError_t launch_entropy_grad(const void *img, const double *stats, const float *scale, void *grad,
+                               long long count, hipStream_t s);
+hipError_t launch_phase_grad(bool fp16_storage, int log2n, const PhaseGradArgs &a, bool fused,
+                             hipStream_t s);
+long long phase_grad_scratch_floats(int log2n);
+
+}  // namespace bfp

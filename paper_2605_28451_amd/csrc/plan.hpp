@@ -1,0 +1,41 @@
+// Plan object shared by the C-ABI translation units (host only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "bfpfft.h"
+
+struct bfp_plan_s {
+  int kind = 0;  // 0: rows, 1: uneven
+  int n = 0, log2n = 0, batch = 0, prec = 0;
+  unsigned flags = 0;
+  int device = 0;
+  void *tw = nullptr;                         // rows: this size's table
+  unsigned long long *nonfinite = nullptr;    // device counter
+  void *phasor = nullptr;                     // n FP32 pairs (rows plans)
+  // uneven plans
+  int count = 0;
+  long long total = 0;
+  std::vector<long long> offsets;
+  int4 *items = nullptr;
+  long long *offsets_d = nullptr;
+  unsigned char *inverse_d = nullptr;
+  int n_items = 0;
+  unsigned *queue = nullptr;
+  int *order_d = nullptr;
+  int grid = 0;
+  // autofocus workspace
+  void *tw32 = nullptr;          // FP32 twiddles (owned only when tw is FP16)
+  double *ent_partial = nullptr; // kEntropyBlocks x 2 doubles
+  float *pg_partial = nullptr;   // phase-gradient partial rows
+  void *tw_sizes[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void **tw_ptrs_d = nullptr;
+};
+
+namespace bfp {
+// Records msg as the calling thread's last error and returns status.
+int set_error(int status, const std::string &msg);
+}  // namespace bfp

@@ -1,0 +1,134 @@
+// Data-movement and helper kernels of the SAR chain: the LDS-tiled corner
+// turn, storage-format conversion and the per-pulse phasor table used by the
+// autofocus phase correction.
+#include "fft_device.hpp"
+#include "internal.hpp"
+
+namespace bfp {
+
+// ------------------------------------------------------------ corner turn --
+// out[c][r] = in[r][c].  A 256-thread workgroup moves a 64 x 64 tile: each
+// wavefront reads 64 consecutive elements of one input row (coalesced),
+// the tile is staged in LDS with one element of padding per row (so the
+// column reads hit distinct banks), and each wavefront writes 64 consecutive
+// elements of one output row.  Tiles are assigned row-major over the output
+// so that consecutive workgroups write neighbouring output rows.
+template <class T>
+__global__ void __launch_bounds__(256) transpose_kernel(const T *__restrict__ in, T *__restrict__ out,
+                                                        int rows, int cols) {
+  __shared__ T tile[64][65];
+  const int tiles_r = (rows + 63) / 64;
+  const int tc = blockIdx.x / tiles_r;  // tile column (input) = tile row of output
+  const int tr = blockIdx.x % tiles_r;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;  // 0..3
+  const int r0 = tr * 64, c0 = tc * 64;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int r = r0 + wv + 4 * i, c = c0 + lane;
+    if (r < rows && c < cols) tile[wv + 4 * i][lane] = in[(size_t)r * cols + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int oc = c0 + wv + 4 * i;  // output row = input column
+    const int orr = r0 + lane;       // output column = input row
+    if (oc < cols && orr < rows) out[(size_t)oc * rows + orr] = tile[lane][wv + 4 * i];
+  }
+}
+
+hipError_t launch_transpose(const void *in, void *out, int rows, int cols, int bytes,
+                            hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const long long tiles = (long long)((rows + 63) / 64) * ((cols + 63) / 64);
+  if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  dim3 grid((unsigned)tiles), block(256);
+  switch (bytes) {
+    case 2:
+      hipLaunchKernelGGL(transpose_kernel<uint16_t>, grid, block, 0, s,
+                         (const uint16_t *)in, (uint16_t *)out, rows, cols);
+      break;
+    case 4:
+      hipLaunchKernelGGL(transpose_kernel<uint32_t>, grid, block, 0, s,
+                         (const uint32_t *)in, (uint32_t *)out, rows, cols);
+      break;
+    case 8:
+      hipLaunchKernelGGL(transpose_kernel<uint2>, grid, block, 0, s, (const uint2 *)in,
+                         (uint2 *)out, rows, cols);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- convert ----
+__device__ __forceinline__ c32 load_fmt(const void *p, long long i, int fmt) {
+  switch (fmt) {
+    case 0: return static_cast<const c32 *>(p)[i];
+    case 1: return h2_to_c32(static_cast<const h2 *>(p)[i]);
+    case 2: {
+      fp8x2 b = static_cast<const fp8x2 *>(p)[i];
+      return c32{fp8_decode<3, 7>(b.x), fp8_decode<3, 7>(b.y)};
+    }
+    default: {
+      fp8x2 b = static_cast<const fp8x2 *>(p)[i];
+      return c32{fp8_decode<2, 15>(b.x), fp8_decode<2, 15>(b.y)};
+    }
+  }
+}
+
+// FP32 -> FP16 rounds once (RNE); FP16/FP8 inputs are exact in FP32, so
+// every conversion below is a single correct rounding of the input value.
+__device__ __forceinline__ void store_fmt(void *p, long long i, int fmt, c32 v) {
+  switch (fmt) {
+    case 0: static_cast<c32 *>(p)[i] = v; break;
+    case 1: static_cast<h2 *>(p)[i] = c32_to_h2(v); break;
+    case 2:
+      static_cast<fp8x2 *>(p)[i] = fp8x2{(uint8_t)fp8_encode<3, 7>(v.x), (uint8_t)fp8_encode<3, 7>(v.y)};
+      break;
+    default:
+      static_cast<fp8x2 *>(p)[i] =
+          fp8x2{(uint8_t)fp8_encode<2, 15>(v.x), (uint8_t)fp8_encode<2, 15>(v.y)};
+      break;
+  }
+}
+
+__global__ void __launch_bounds__(256) convert_kernel(const void *in, int in_fmt, void *out,
+                                                      int out_fmt, long long count) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    store_fmt(out, i, out_fmt, load_fmt(in, i, in_fmt));
+}
+
+hipError_t launch_convert(const void *in, int in_fmt, void *out, int out_fmt, long long count,
+                          hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  long long blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, in_fmt, out,
+                     out_fmt, count);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- phasor ----
+// p[m] = exp(+/- i phase[m]) for the per-pulse phase correction; evaluated in
+// FP64 from the FP32 radians and rounded once to FP32.
+__global__ void __launch_bounds__(256) phasor_kernel(const float *__restrict__ phase,
+                                                     c32 *__restrict__ p, int n, int negate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    double s, c;
+    sincos((double)phase[i], &s, &c);
+    p[i] = c32{(float)c, (float)(negate ? -s : s)};
+  }
+}
+
+hipError_t launch_phasor(const float *phase, void *phasor, int n, int negate, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(phasor_kernel, dim3((n + 255) / 256), dim3(256), 0, s, phase,
+                     static_cast<c32 *>(phasor), n, negate);
+  return hipGetLastError();
+}
+
+}  // namespace bfp

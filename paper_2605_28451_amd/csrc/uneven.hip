@@ -1,0 +1,133 @@
+// Persistent kernel for a batch of transforms of uneven length and mixed
+// direction, one launch for the whole batch.  Compiled once per precision
+// mode with -DBFP_MODE_ID.
+//
+// The host groups transforms of equal length into work items that fill one
+// 1024-thread workgroup (16384/N transforms of length N, 16 elements per
+// thread; 16 transforms of 512 with 8 per thread) and orders the items
+// longest transform first.  A grid sized to the resident occupancy pulls
+// items from a device counter until the queue is empty, so the load balances
+// across the 256 CUs without a second launch.  Every workgroup leaves the
+// loop when the counter passes the item count, so the grid always drains.
+#include "fft_engine.hpp"
+#include "internal.hpp"
+
+#ifndef BFP_MODE_ID
+#error "BFP_MODE_ID must be defined"
+#endif
+
+namespace bfp {
+
+#if BFP_MODE_ID == 0
+typedef ModeFP32 MODE;
+#elif BFP_MODE_ID == 1
+typedef ModeFP16 MODE;
+#elif BFP_MODE_ID == 2
+typedef ModeF16StoreF32 MODE;
+#elif BFP_MODE_ID == 3
+typedef ModeF16MulF32Acc MODE;
+#elif BFP_MODE_ID == 4
+typedef ModeE4M3 MODE;
+#elif BFP_MODE_ID == 5
+typedef ModeE5M2 MODE;
+#else
+#error "unknown BFP_MODE_ID"
+#endif
+
+constexpr int UNEVEN_WG = 1024;
+constexpr int UNEVEN_LDS = 16384 + 16384 / 16;  // largest per-item LDS (elements)
+
+template <class M, int LOG2N>
+__device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typename M::Lds *lds_all) {
+  typedef Geometry<LOG2N> G;
+  typedef Engine<M, LOG2N> EN;
+  typedef typename M::Comp Comp;
+  typedef typename M::Store Store;
+  constexpr int E = G::E, T = G::T, N = G::N;
+  static_assert((UNEVEN_WG / T) * G::LDS_N <= UNEVEN_LDS, "item exceeds LDS");
+  constexpr float inv_n = 1.0f / (float)N;
+  const int local = threadIdx.x / T;
+  const int t = threadIdx.x & (T - 1);
+  const bool active = local < d.y;
+  long long off = 0;
+  bool inv = false;
+  if (active) {
+    const int idx = a.order[d.x + local];
+    off = a.offsets[idx];
+    inv = a.inverse[idx] != 0;
+  }
+  Comp v[E];
+  if (active) {
+    const Store *src = static_cast<const Store *>(a.in) + off;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      Comp z = M::load(src, t + T * e);
+      v[e] = inv ? cscale(cconj(z), inv_n) : z;  // BFP fold for inverse transforms
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = Comp{};
+  }
+  EN::run(v, lds_all + local * G::LDS_N, static_cast<const typename M::Tw *>(a.tw[LOG2N - 8]), t);
+  if (active) {
+    Store *dst = static_cast<Store *>(a.out) + off;
+    unsigned bad = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      Comp y = inv ? cconj(v[e]) : v[e];
+      M::store(dst, t + T * e, y);
+      if (a.flags & KF_CHECK_FINITE) bad += finite_c(to_c32(M::round_store(y))) ? 0u : 1u;
+    }
+    if (bad) atomicAdd(a.nonfinite, (unsigned long long)bad);
+  }
+}
+
+template <class M>
+__global__ void uneven_reset_kernel(unsigned *queue) { *queue = 0u; }
+
+template <class M>
+__global__ void __launch_bounds__(UNEVEN_WG) uneven_kernel(UnevenArgs a) {
+  __shared__ typename M::Lds lds[UNEVEN_LDS];
+  __shared__ int item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = (int)atomicAdd(a.queue, 1u);
+    __syncthreads();
+    const int it = item_s;
+    __syncthreads();  // every thread has read item_s before it is rewritten
+    if (it >= a.n_items) break;
+    const int4 d = a.items[it];
+    switch (d.z) {
+      case 8: uneven_item<M, 8>(a, d, lds); break;
+      case 9: uneven_item<M, 9>(a, d, lds); break;
+      case 10: uneven_item<M, 10>(a, d, lds); break;
+      case 11: uneven_item<M, 11>(a, d, lds); break;
+      case 12: uneven_item<M, 12>(a, d, lds); break;
+      case 13: uneven_item<M, 13>(a, d, lds); break;
+      case 14: uneven_item<M, 14>(a, d, lds); break;
+      default: break;
+    }
+    __syncthreads();  // LDS of this item is free before the next one
+  }
+}
+
+#define BFP_CAT2(a, b) a##b
+#define BFP_CAT(a, b) BFP_CAT2(a, b)
+
+hipError_t BFP_CAT(launch_uneven_mode, BFP_MODE_ID)(const UnevenArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(uneven_reset_kernel<MODE>, dim3(1), dim3(1), 0, s, a.queue);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(uneven_kernel<MODE>, dim3(grid), dim3(UNEVEN_WG), 0, s, a);
+  return hipGetLastError();
+}
+
+int BFP_CAT(uneven_blocks_per_cu_mode, BFP_MODE_ID)() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, uneven_kernel<MODE>, UNEVEN_WG, 0) !=
+      hipSuccess)
+    return 1;
+  return blocks < 1 ? 1 : blocks;
+}
+
+}  // namespace bfp

@@ -1,0 +1,104 @@
+"""Differentiable azimuth compression and entropy autofocus (GPU tier).
+
+The GPU gradient of the image entropy with respect to the per-pulse phase
+vector is checked against the FP64 oracle's analytic gradient and against
+FP64 central finite differences of the oracle's entropy.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_28451_amd import api, scenes
+from paper_2605_28451_amd.autofocus import (AutofocusPlan, AzimuthFocus, ImageEntropy,
+                                            entropy_and_grad)
+from tests.gpu_util import announce, need_gpu, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_case(seed=5, nr=128, npul=1024):
+    rng = np.random.default_rng(seed)
+    sc = scenes.sar_scene(seed=seed, n=npul, length=64, aperture=128, ranges=(40, 80),
+                          azimuths=(300, 700))
+    Hr = oracle.matched_filter(sc.range_replica, npul)
+    rc = oracle.compress(sc.echo, Hr)          # [pulse][range]
+    rc_t = np.ascontiguousarray(rc.T[:nr])     # [range][pulse], nr range bins
+    phi = 0.5 * rng.standard_normal(npul)
+    return sc, rc_t, phi
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp16_fp32"])
+def test_phase_gradient_matches_fp64(mode):
+    need_gpu()
+    announce(f"autofocus gradient small mode={mode}")
+    sc, rc_t, phi = _small_case()
+    nr, npul = rc_t.shape
+    fmt = api.storage_format(mode)
+    rcq = scenes.quantize(rc_t, fmt)
+    phi32 = phi.astype(np.float32).astype(np.float64)
+    Ha = api.filter_tensor(sc.azimuth_replica, npul, mode)
+    Haq = scenes.quantize(oracle.matched_filter(sc.azimuth_replica, npul), api.filter_format(mode))
+    E_ref, g_ref = oracle.autofocus(rcq, Haq, phi32)
+    plan = AutofocusPlan(npul, nr, mode)
+    ph = torch.tensor(phi32, dtype=torch.float32, device="cuda")
+    E, g, _ = entropy_and_grad(plan, upload(rcq, fmt), Ha, ph)
+    E = float(E.item())
+    g = g.cpu().numpy().astype(np.float64)
+    tol = 1e-4 if mode == "fp32" else 2e-3
+    assert abs(E - E_ref) <= tol * abs(E_ref)
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    cos = np.dot(g, g_ref) / np.linalg.norm(g) / np.linalg.norm(g_ref)
+    print(f"mode={mode} E={E:.6f} ref={E_ref:.6f} grad rel err {rel:.2e} cos {cos:.6f}")
+    assert rel <= (1e-3 if mode == "fp32" else 2e-2)
+    assert cos >= 0.9999
+    # constant-phase invariance: sum_m dE/dphi_m = 0
+    assert abs(g.sum()) <= 1e-3 * np.abs(g).sum()
+    # FP64 central differences of the oracle's entropy at a few pulses
+    h = 1e-4
+    for m in np.argsort(-np.abs(g_ref))[:3]:
+        pp = phi32.copy(); pp[m] += h
+        pm = phi32.copy(); pm[m] -= h
+        fd = (oracle.autofocus(rcq, Haq, pp)[0] - oracle.autofocus(rcq, Haq, pm)[0]) / (2 * h)
+        assert abs(g[m] - fd) <= max(5e-2 * abs(fd), 1e-6), (m, g[m], fd)
+
+
+def test_autograd_path_equals_fused_path():
+    need_gpu()
+    sc, rc_t, phi = _small_case(seed=6)
+    nr, npul = rc_t.shape
+    rcd = upload(scenes.quantize(rc_t, "fp16"), "fp16")
+    plan = AutofocusPlan(npul, nr, "fp16_fp32")
+    Ha = api.filter_tensor(sc.azimuth_replica, npul, "fp16_fp32")
+    ph = torch.tensor(phi, dtype=torch.float32, device="cuda", requires_grad=True)
+    E = ImageEntropy.apply(AzimuthFocus.apply(ph, plan, rcd, Ha), plan)
+    E.backward()
+    E2, g2, _ = entropy_and_grad(plan, rcd, Ha, ph.detach())
+    torch.cuda.synchronize()
+    assert abs(float(E) - float(E2)) <= 1e-9 * abs(float(E2))
+    ga, gf = ph.grad.cpu().numpy(), g2.cpu().numpy()
+    assert np.linalg.norm(ga - gf) <= 1e-4 * np.linalg.norm(gf)
+
+
+def test_adjoint_dot_product_identity():
+    # <A z, y> = <z, A^H y> through the autograd Function: for a linear loss
+    # L = Re<y, A(z e^{i phi})>, dL/dphi_m = sum_r Im(A^H(y)[r,m] conj(z[r,m]))
+    need_gpu()
+    rng = np.random.default_rng(1)
+    nr, npul = 64, 512
+    rc = scenes.quantize(0.1 * (rng.standard_normal((nr, npul)) + 1j * rng.standard_normal((nr, npul))), "fp32")
+    rep = np.exp(1j * rng.uniform(0, 6, npul))
+    y = rng.standard_normal((nr, npul)) + 1j * rng.standard_normal((nr, npul))
+    phi = rng.uniform(-1, 1, npul)
+    plan = AutofocusPlan(npul, nr, "fp32")
+    Ha = api.filter_tensor(rep, npul, "fp32")
+    H = scenes.quantize(oracle.matched_filter(rep, npul), "fp32")
+    ph = torch.tensor(phi, dtype=torch.float32, device="cuda", requires_grad=True)
+    img = AzimuthFocus.apply(ph, plan, upload(rc, "fp32"), Ha)
+    yt = torch.tensor(np.stack([y.real, y.imag], -1), dtype=torch.float32, device="cuda")
+    L = (img * yt).sum()
+    L.backward()
+    z = rc * np.exp(1j * phi.astype(np.float32))[None]
+    ref = np.sum(np.imag(oracle.compress(y, H, conj_filter=True) * np.conj(z)), axis=0)
+    got = ph.grad.cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)

@@ -1,0 +1,150 @@
+"""Parity of the fused SAR kernels with the FP64 oracle (GPU tier)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import metrics
+from oracle.metrics import sqnr_db
+from paper_2605_28451_amd import api, scenes
+from tests.gpu_util import announce, download, need_gpu, upload
+
+pytestmark = pytest.mark.gpu
+
+RC_SQNR_MIN = {"fp32": 120.0, "fp16": 45.0, "fp16_fp32": 50.0, "fp16_mul_fp32_acc": 50.0,
+               "e4m3": 12.0, "e5m2": 6.0}
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp16", "fp16_fp32", "fp16_mul_fp32_acc", "e4m3", "e5m2"])
+def test_range_compression_matches_oracle(mode):
+    # range-compression scene (5 LFM targets, 20 dB noise), 256 of its pulses
+    need_gpu()
+    announce(f"range compression 256x4096 mode={mode}")
+    sc = scenes.range_scene(seed=2, n_pulses=256)
+    fmt = api.storage_format(mode)
+    ffmt = api.filter_format(mode)
+    echo = scenes.quantize(sc.echo, fmt)
+    H = scenes.quantize(oracle.matched_filter(sc.replica, 4096), ffmt)
+    ref = oracle.compress(echo, H)
+    plan = api.FFTPlan(4096, 256, mode, flags=api.FLAG_CHECK_FINITE)
+    Hd = api.filter_tensor(sc.replica, 4096, mode)
+    rc = download(plan.range_compress(upload(echo, fmt), Hd), fmt)
+    assert plan.nonfinite() == 0
+    s = sqnr_db(ref, rc, align=True)
+    print(f"mode={mode} range-compression SQNR {s:.2f} dB")
+    assert s >= RC_SQNR_MIN[mode]
+    # peaks at the target delays
+    for d in sc.delays:
+        assert np.argmax(np.abs(rc[0, max(d - 3, 0):d + 4])) + max(d - 3, 0) == d
+
+
+@pytest.mark.parametrize("mode", ["fp16", "fp16_fp32"])
+def test_range_compression_naive_overflows(mode):
+    need_gpu()
+    sc = scenes.range_scene(seed=2, n_pulses=16)
+    fmt = api.storage_format(mode)
+    plan = api.FFTPlan(4096, 16, mode, flags=api.FLAG_CHECK_FINITE)
+    Hd = api.filter_tensor(sc.replica, 4096, mode)
+    rc = download(plan.range_compress(upload(sc.echo, fmt), Hd, naive=True), fmt)
+    assert not np.all(np.isfinite(rc))
+    assert plan.nonfinite() > 0
+
+
+def test_filter_matches_oracle_rounding():
+    # host FP64 filter (library) vs oracle filter rounded by numpy
+    need_gpu()
+    sc = scenes.range_scene(seed=2, n_pulses=1)
+    H = oracle.matched_filter(sc.replica, 4096)
+    for fmt in ("fp16", "fp32"):
+        got = scenes.decode(api.make_filter(sc.replica, 4096, fmt), fmt)
+        want = scenes.quantize(H, fmt)
+        assert np.mean(got == want) > 0.999
+        assert np.max(np.abs(got - want)) <= 2 ** -10
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "fp32", "e4m3"])
+def test_corner_turn_exact(fmt):
+    need_gpu()
+    rng = np.random.default_rng(0)
+    for rows, cols in [(4096, 4096), (100, 260), (64, 1)]:
+        announce(f"corner turn {rows}x{cols} {fmt}")
+        x = scenes.quantize(0.1 * (rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))), fmt)
+        y = download(api.corner_turn(upload(x, fmt), fmt), fmt)
+        assert np.array_equal(y, x.T)
+
+
+@pytest.mark.parametrize("src,dst", [("fp32", "fp16"), ("fp32", "e4m3"), ("fp32", "e5m2"),
+                                     ("fp16", "e4m3"), ("e4m3", "fp32"), ("e5m2", "fp16")])
+def test_convert_matches_host_encoder(src, dst):
+    need_gpu()
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal(5000) * 10.0 ** rng.uniform(-6, 5, 5000)
+    x = scenes.quantize(v[:2500] + 1j * v[2500:], src)
+    with np.errstate(over="ignore"):
+        want = scenes.encode(scenes.decode(scenes.encode(x, src), src), dst)
+    got = api.convert(upload(x, src), src, dst)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+
+
+def _gpu_frame(sc, mode, phase=None):
+    """range compress -> corner turn -> azimuth compress on the GPU."""
+    fmt = api.storage_format(mode)
+    npul, nr = sc.echo.shape
+    rplan = api.FFTPlan(nr, npul, mode, flags=api.FLAG_CHECK_FINITE)
+    aplan = api.FFTPlan(npul, nr, mode, flags=api.FLAG_CHECK_FINITE)
+    Hr = api.filter_tensor(sc.range_replica, nr, mode)
+    Ha = api.filter_tensor(sc.azimuth_replica, npul, mode)
+    rc = rplan.range_compress(upload(scenes.quantize(sc.echo, fmt), fmt), Hr)
+    rct = api.corner_turn(rc, fmt)
+    ph = None if phase is None else torch.tensor(phase, dtype=torch.float32, device="cuda")
+    img = aplan.azimuth_compress(rct, Ha, phase=ph)
+    out = download(img, fmt)
+    assert rplan.nonfinite() == 0 and aplan.nonfinite() == 0
+    return out
+
+
+def _oracle_frame(sc, mode, phase=None):
+    fmt = api.storage_format(mode)
+    ffmt = api.filter_format(mode)
+    Hr = scenes.quantize(oracle.matched_filter(sc.range_replica, sc.echo.shape[1]), ffmt)
+    Ha = scenes.quantize(oracle.matched_filter(sc.azimuth_replica, sc.echo.shape[0]), ffmt)
+    return oracle.sar_image(scenes.quantize(sc.echo, fmt), Hr, Ha, phi=phase)
+
+
+FRAME_SQNR_MIN = {"fp16": 40.0, "fp16_fp32": 45.0, "fp16_mul_fp32_acc": 45.0, "fp32": 110.0,
+                  "e4m3": 10.0, "e5m2": 5.0}
+
+
+@pytest.mark.parametrize("mode", ["fp16", "fp16_fp32", "fp16_mul_fp32_acc", "fp32", "e4m3", "e5m2"])
+def test_sar_frame_4096_matches_oracle_metrics(mode):
+    # full range-Doppler frame, 4096 x 4096, 3 x 3 point targets
+    need_gpu()
+    announce(f"SAR frame 4096x4096 mode={mode}")
+    sc = scenes.sar_scene(seed=3)
+    img = _gpu_frame(sc, mode)
+    ref = _oracle_frame(sc, mode)
+    s = metrics.sqnr_db(ref, img, align=True)
+    print(f"mode={mode} frame SQNR {s:.2f} dB")
+    assert np.all(np.isfinite(img))
+    assert s >= FRAME_SQNR_MIN[mode]
+    if mode in ("e4m3", "e5m2"):
+        return
+    for (r0, a0) in sc.targets:
+        mg = metrics.point_target(img, r0, a0, noise_patch=(r0 + 300, a0 + 300))
+        mo = metrics.point_target(ref, r0, a0, noise_patch=(r0 + 300, a0 + 300))
+        assert mg["peak_rc"] == mo["peak_rc"] == (r0, a0)
+        for k in ("pslr_range", "pslr_azimuth", "islr_range", "islr_azimuth", "snr"):
+            assert abs(mg[k] - mo[k]) <= 0.1, (r0, a0, k, mg[k], mo[k])
+        for k in ("irw_range", "irw_azimuth"):
+            assert abs(mg[k] - mo[k]) <= 0.02, (r0, a0, k, mg[k], mo[k])
+
+
+def test_azimuth_phase_correction_matches_oracle():
+    need_gpu()
+    sc = scenes.sar_scene(seed=3, n=1024, length=256, aperture=128, ranges=(300,), azimuths=(512,))
+    rng = np.random.default_rng(3)
+    phi = rng.uniform(-3, 3, 1024).astype(np.float32).astype(np.float64)
+    img = _gpu_frame(sc, "fp16_fp32", phase=phi)
+    ref = _oracle_frame(sc, "fp16_fp32", phase=phi)
+    assert metrics.sqnr_db(ref, img, align=True) >= 45.0
