@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -121,11 +123,139 @@ def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30):
     return res
 
 
+def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True):
+    """Full 4096x4096 range-Doppler frame: fused range compression, LDS-tiled
+    corner turn, fused azimuth compression.  n_frames independent frame
+    buffer sets rotate (4 x 256 MiB for FP16) and the K frames of a replay
+    are captured once in a HIP graph."""
+    import torch
+    from paper_2605_28451_amd import api, scenes
+    fmt = api.storage_format(mode)
+    sc = scenes.sar_scene(seed=3)
+    n = 4096
+    echo0 = api.to_device(sc.echo, fmt)
+    echoes = [echo0] + [echo0.clone() for _ in range(n_frames - 1)]
+    rcs = [torch.empty_like(echo0) for _ in range(n_frames)]
+    rcts = [torch.empty_like(echo0) for _ in range(n_frames)]
+    imgs = [torch.empty_like(echo0) for _ in range(n_frames)]
+    rplan = api.FFTPlan(n, n, mode)
+    aplan = api.FFTPlan(n, n, mode)
+    Hr = api.filter_tensor(sc.range_replica, n, mode)
+    Ha = api.filter_tensor(sc.azimuth_replica, n, mode)
+
+    def frame(i):
+        rplan.range_compress(echoes[i], Hr, out=rcs[i])
+        api.corner_turn(rcs[i], fmt, out=rcts[i])
+        aplan.azimuth_compress(rcts[i], Ha, out=imgs[i])
+
+    for i in range(warmup):
+        frame(i % n_frames)
+    torch.cuda.synchronize()
+    reps = max(1, steps // n_frames)
+    if graph:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for i in range(n_frames):
+                    frame(i)
+        torch.cuda.current_stream().wait_stream(s)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / (reps * n_frames)
+    else:
+        per, total = time_launches(frame, n_frames, reps * n_frames, 0)
+        ms = total / (reps * n_frames)
+    bytes_frame = 6 * echo0.numel() * echo0.element_size()  # RC r/w, CT r/w, AC r/w
+    res = {"mode": mode, "ms_per_frame": ms, "frames_per_s": 1e3 / ms,
+           "hbm_gbs": bytes_frame / (ms * 1e-3) / 1e9, "bytes_per_frame": bytes_frame,
+           "gflops": fft_flops(n, 4 * n) / (ms * 1e-3) / 1e9, "graph": graph,
+           "frames_rotating": n_frames}
+    torch.cuda.synchronize()
+    res["_img"] = api.to_host(imgs[0], fmt)
+    res["_scene"] = sc
+    del echoes, rcs, rcts, imgs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_uneven(mode, steps, warmup):
+    import torch
+    from paper_2605_28451_amd import api, scenes
+    ub = scenes.uneven_batch(seed=4, count=20000)
+    fmt = api.storage_format(mode)
+    x0 = api.to_device(ub.x, fmt)
+    sets = 2
+    ins = [x0, x0.clone()]
+    outs = [torch.empty_like(x0) for _ in range(sets)]
+    plan = api.UnevenPlan(ub.log2n, ub.inverse, mode)
+    per, total = time_launches(lambda i: plan.execute(ins[i], out=outs[i]), sets, steps, warmup)
+    ms = total / steps
+    sizes = (1 << ub.log2n.astype("int64"))
+    import numpy as np
+    flops = float(np.sum(5.0 * sizes * ub.log2n))
+    bytes_ = 2 * x0.numel() * x0.element_size()
+    res = {"mode": mode, "transforms": 20000, "ms_per_launch": ms,
+           "gflops": flops / (ms * 1e-3) / 1e9, "hbm_gbs": bytes_ / (ms * 1e-3) / 1e9,
+           "bytes_per_launch": bytes_}
+    del ins, outs, x0
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_autofocus(steps, lr=0.3):
+    """50 Adam steps of entropy autofocus on a 4096x4096 frame with the
+    injected per-pulse phase error; returns ms/step and PSLR before/after."""
+    import numpy as np
+    import torch
+    from paper_2605_28451_amd import api, scenes
+    from paper_2605_28451_amd.autofocus import AutofocusPlan, entropy_and_grad
+    n = 4096
+    perr = scenes.autofocus_phase_error(seed=5, n_pulse=n)
+    sc = scenes.sar_scene(seed=3, phase_error=perr)
+    mode = "fp16_fp32"
+    rplan = api.FFTPlan(n, n, mode)
+    Hr = api.filter_tensor(sc.range_replica, n, mode)
+    rc = rplan.range_compress(api.to_device(sc.echo, "fp16"), Hr)
+    rct = api.corner_turn(rc, "fp16")
+    plan = AutofocusPlan(n, n, mode)
+    Ha = api.filter_tensor(sc.azimuth_replica, n, mode)
+    phi = torch.zeros(n, dtype=torch.float32, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([phi], lr=lr)
+    img = torch.empty((n, n, 2), dtype=torch.float32, device="cuda")
+    stats = torch.empty(3, dtype=torch.float64, device="cuda")
+    grad = torch.empty(n, dtype=torch.float32, device="cuda")
+    E0, _, _ = entropy_and_grad(plan, rct, Ha, phi.detach(), img=img, stats=stats, grad=grad)
+    E0 = float(E0)
+    img0 = api.to_host(img, "fp32")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        E, g, _ = entropy_and_grad(plan, rct, Ha, phi.detach(), img=img, stats=stats, grad=grad)
+        phi.grad = g
+        opt.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    E, _, _ = entropy_and_grad(plan, rct, Ha, phi.detach(), img=img, stats=stats, grad=grad)
+    img1 = api.to_host(img, "fp32")
+    return {"ms_per_step": ms, "steps": steps, "lr": lr, "entropy_before": E0,
+            "entropy_after": float(E), "_img0": img0, "_img1": img1, "_scene": sc}
+
+
 def cpu_baseline(sample_in, replica, n, sample_out):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload."""
     import numpy as np
     import oracle
-    from oracle.metrics import sqnr_db
+    from paper_2605_28451_amd.metrics import sqnr_db
     from paper_2605_28451_amd import scenes
     H = oracle.matched_filter(replica, n)
     Hq = scenes.quantize(H, "fp16")
@@ -156,6 +286,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--kernel-only", default=None,
+                    help="profiling mode: run only the fused range-compression kernel of the "
+                         "given precision (e.g. fp16) for --steps launches, then a plain device "
+                         "copy of the same bytes (counter calibration); prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
@@ -169,6 +303,19 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     n, rows = 4096, 2048
+    if args.kernel_only:
+        r = bench_compress(args.kernel_only, rows, n, args.steps, args.warmup)
+        print(f"[kernel-only] {args.kernel_only} compress: {r['ms_per_launch']:.4f} ms/launch "
+              f"{r['hbm_gbs']:.0f} GB/s algorithmic ({r['bytes_per_launch']} B/launch)",
+              file=sys.stderr, flush=True)
+        buf_in = torch.empty(r["bytes_per_launch"] // 2, dtype=torch.uint8, device="cuda")
+        buf_out = torch.empty_like(buf_in)
+        per, _ = time_launches(lambda i: api.device_copy(buf_in, buf_out), 1, args.steps, args.warmup)
+        ms = sum(per) / len(per)
+        print(f"[kernel-only] device copy of {buf_in.numel()} B: {ms:.4f} ms, "
+              f"{2 * buf_in.numel() / (ms * 1e-3) / 1e9:.0f} GB/s (read + write)",
+              file=sys.stderr, flush=True)
+        return
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
 
     log("headline: fused FP16-BFP range compression 2048x4096")
@@ -223,7 +370,8 @@ def main():
         out["range_compress_modes"] = modes
         out["fp16_over_fp32"] = round(head["gflops"] / modes["fp32"]["gflops"], 3)
         fft = {}
-        for mode, b in (("fp16", 65536), ("fp32", 32768), ("fp16_fp32", 65536)):
+        for mode, b in (("fp16", 65536), ("fp32", 32768), ("fp16_fp32", 65536),
+                        ("fp16_mul_fp32_acc", 65536)):
             log(f"plain forward FFT n=4096 batch={b} mode={mode}")
             r = bench_fft(mode, b, n, args.steps, args.warmup)
             fft[mode] = {k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}
@@ -231,6 +379,40 @@ def main():
         r = bench_fft("fp16", 64, n, args.steps, args.warmup, min_bytes=0)
         fft["fp16_batch64"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}
         out["fft_n4096"] = fft
+        from paper_2605_28451_amd import metrics as _m  # noqa: F401  (metrics of the GPU image only)
+        sar = {}
+        for mode in ("fp16", "fp32", "fp16_fp32", "fp16_mul_fp32_acc"):
+            log(f"SAR frame 4096x4096 mode={mode} (graph)")
+            r = bench_sar_frame(mode, args.steps, args.warmup)
+            sar[mode] = {k: (round(v, 4) if isinstance(v, float) else v)
+                         for k, v in r.items() if not k.startswith("_")}
+            if mode == "fp16":
+                sc = r["_scene"]
+                pts = [_m.point_target(r["_img"], r0, a0, noise_patch=(r0 + 300, a0 + 300))
+                       for (r0, a0) in sc.targets]
+                sar["fp16_metrics"] = {
+                    "pslr_range_db_mean": round(float(np.mean([p["pslr_range"] for p in pts])), 3),
+                    "pslr_azimuth_db_mean": round(float(np.mean([p["pslr_azimuth"] for p in pts])), 3),
+                    "snr_db_mean": round(float(np.mean([p["snr"] for p in pts])), 2),
+                }
+        out["sar_frame_4096"] = sar
+        out["sar_frames_per_s_fp16"] = sar["fp16"]["frames_per_s"]
+        log("uneven batch 20000 transforms fp16")
+        ub = bench_uneven("fp16", args.steps, args.warmup)
+        out["uneven_20000"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in ub.items()}
+        log("autofocus 50 Adam steps 4096x4096")
+        af = bench_autofocus(50)
+        sc = af["_scene"]
+        before = [_m.point_target(af["_img0"], r0, a0, search=64) for (r0, a0) in sc.targets]
+        after = [_m.point_target(af["_img1"], r0, a0, search=64) for (r0, a0) in sc.targets]
+        out["autofocus_4096"] = {
+            "ms_per_step": round(af["ms_per_step"], 4), "steps": af["steps"], "lr": af["lr"],
+            "entropy_before": round(af["entropy_before"], 5), "entropy_after": round(af["entropy_after"], 5),
+            "pslr_azimuth_db_before": round(float(np.mean([p["pslr_azimuth"] for p in before])), 2),
+            "pslr_azimuth_db_after": round(float(np.mean([p["pslr_azimuth"] for p in after])), 2),
+            "peak_power_gain_db": round(float(10 * np.log10(np.mean([p["peak_power"] for p in after]) /
+                                                          np.mean([p["peak_power"] for p in before]))), 2),
+        }
     print(json.dumps(out), flush=True)
 
 

@@ -134,6 +134,24 @@ int fft_exec_inv_bfp(bfp_plan p, const void *in, void *out, const void *filter,
 int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *filter,
                            unsigned flags, void *stream);
 
+/* Tuning knobs of a plan.  engine: 0 = matrix cores where the mode and size
+ * have them (BFP_FP16_MUL_FP32_ACC at n = 4096), 1 = vector ALU only.
+ * blocks_per_cu: rows plans: 0 = one workgroup per group of rows, k > 0 = a
+ * persistent grid of k workgroups per CU looping over the rows; uneven plans:
+ * workgroups per CU of the persistent launch (0 or above the resident
+ * maximum = the maximum).  Results do not depend on blocks_per_cu. */
+int fft_plan_set_tuning(bfp_plan p, int engine, int blocks_per_cu);
+int fft_plan_get_tuning(bfp_plan p, int *engine, int *blocks_per_cu);
+
+/* Times every tuning candidate of the plan on the caller's buffers (op: 0
+ * forward, 1 BFP inverse with `filter` (may be NULL), 2 fused compression
+ * with `filter`; ignored for uneven plans), `reps` calls each after two
+ * warm-up calls, keeps the fastest in the plan and returns its mean time per
+ * call in *best_ms (may be NULL).  `out` is overwritten; synchronises
+ * `stream`. */
+int fft_autotune(bfp_plan p, int op, const void *in, void *out, const void *filter, int reps,
+                 float *best_ms, void *stream);
+
 /* Reads and clears the plan's non-finite counter; synchronises `stream`. */
 int fft_plan_nonfinite(bfp_plan p, void *stream, unsigned long long *count);
 
@@ -165,6 +183,11 @@ int bfp_make_filter(const double *h, int len, int n, int fmt, void *out_host);
  * value (E4M3: 448, E5M2: 57344).  in != out. */
 int bfp_convert(const void *in, int in_fmt, void *out, int out_fmt, long long count,
                 void *stream);
+
+/* Plain streaming copy of `bytes` (multiple of 16; 16-byte aligned
+ * pointers), 16 bytes per lane: the reference for achievable HBM bandwidth
+ * and for calibrating hardware memory counters against known traffic. */
+int bfp_device_copy(const void *in, void *out, long long bytes, void *stream);
 
 /* --------------------------------------------------------------- SAR --- */
 /* Fused range compression (Fig. 1, left group): per pulse row,

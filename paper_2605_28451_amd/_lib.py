@@ -53,12 +53,16 @@ SIGNATURES = {
     "fft_exec_inv_bfp": (_I, [_P, _P, _P, _P, _P]),
     "fft_exec_inv_bfp_flags": (_I, [_P, _P, _P, _P, _U, _P]),
     "fft_plan_nonfinite": (_I, [_P, _P, ctypes.POINTER(ctypes.c_ulonglong)]),
+    "fft_plan_set_tuning": (_I, [_P, _I, _I]),
+    "fft_plan_get_tuning": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "fft_autotune": (_I, [_P, _I, _P, _P, _P, _I, ctypes.POINTER(ctypes.c_float), _P]),
     "fft_plan_uneven": (_I, [ctypes.POINTER(_P), _I, _P, _P, _I, _U]),
     "fft_uneven_offsets": (_I, [_P, ctypes.POINTER(_LL)]),
     "fft_uneven_total": (_I, [_P, ctypes.POINTER(_LL)]),
     "fft_exec_uneven": (_I, [_P, _P, _P, _P]),
     "bfp_make_filter": (_I, [_P, _I, _I, _I, _P]),
     "bfp_convert": (_I, [_P, _I, _P, _I, _LL, _P]),
+    "bfp_device_copy": (_I, [_P, _P, _LL, _P]),
     "sar_range_compress": (_I, [_P, _P, _P, _P, _I, _U, _P]),
     "sar_corner_turn": (_I, [_P, _P, _I, _I, _I, _P]),
     "sar_azimuth_compress": (_I, [_P, _P, _P, _P, _P, _I, _I, _U, _P]),

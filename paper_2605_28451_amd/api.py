@@ -87,6 +87,16 @@ def convert(x, in_fmt: str, out_fmt: str, out=None, stream=None):
     return out
 
 
+def device_copy(src, dst, stream=None):
+    """Streaming copy of a whole tensor (bytes a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    check(_lib.load().bfp_device_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)),
+          "bfp_device_copy")
+    return dst
+
+
 def corner_turn(x, fmt: str, out=None, stream=None):
     """out[c][r] = x[r][c] for a (rows, cols, 2) storage tensor."""
     rows, cols = x.shape[0], x.shape[1]
@@ -170,6 +180,25 @@ class FFTPlan:
                                                _stream(stream)), "sar_azimuth_compress")
         return out
 
+
+    # ------------------------------------------------------------ tuning
+    def set_tuning(self, engine: int = 0, blocks_per_cu: int = 0):
+        check(_lib.load().fft_plan_set_tuning(self._h, int(engine), int(blocks_per_cu)),
+              "fft_plan_set_tuning")
+
+    def get_tuning(self):
+        e, b = ctypes.c_int(), ctypes.c_int()
+        check(_lib.load().fft_plan_get_tuning(self._h, ctypes.byref(e), ctypes.byref(b)),
+              "fft_plan_get_tuning")
+        return int(e.value), int(b.value)
+
+    def autotune_on(self, op: int, x, out, filt=None, reps: int = 20, stream=None) -> float:
+        """Time every tuning candidate on (x, out), keep the fastest; returns ms/call."""
+        ms = ctypes.c_float()
+        check(_lib.load().fft_autotune(self._h, int(op), _ptr(x), _ptr(out), _ptr(filt), int(reps),
+                                       ctypes.byref(ms), _stream(stream)), "fft_autotune")
+        return float(ms.value)
+
     def nonfinite(self, stream=None) -> int:
         c = ctypes.c_ulonglong()
         check(_lib.load().fft_plan_nonfinite(self._h, _stream(stream), ctypes.byref(c)),
@@ -222,6 +251,24 @@ class UnevenPlan:
         if self.count:
             check(lib.fft_uneven_offsets(self._h, self.offsets.ctypes.data_as(
                 ctypes.POINTER(ctypes.c_longlong))), "fft_uneven_offsets")
+
+    # ------------------------------------------------------------ tuning
+    def set_tuning(self, engine: int = 0, blocks_per_cu: int = 0):
+        check(_lib.load().fft_plan_set_tuning(self._h, int(engine), int(blocks_per_cu)),
+              "fft_plan_set_tuning")
+
+    def get_tuning(self):
+        e, b = ctypes.c_int(), ctypes.c_int()
+        check(_lib.load().fft_plan_get_tuning(self._h, ctypes.byref(e), ctypes.byref(b)),
+              "fft_plan_get_tuning")
+        return int(e.value), int(b.value)
+
+    def autotune_on(self, op: int, x, out, filt=None, reps: int = 20, stream=None) -> float:
+        """Time every tuning candidate on (x, out), keep the fastest; returns ms/call."""
+        ms = ctypes.c_float()
+        check(_lib.load().fft_autotune(self._h, int(op), _ptr(x), _ptr(out), _ptr(filt), int(reps),
+                                       ctypes.byref(ms), _stream(stream)), "fft_autotune")
+        return float(ms.value)
 
     def execute(self, x, out=None, stream=None):
         _check_storage(x, self.fmt, self.total, "input")

@@ -24,8 +24,14 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}",
           "-Wall", "-Wno-unused-function"]
+# -packed-fp32-ops: no v_pk_*_f32 selection.  -dot5-insts: select the VOP3P
+# v_dot2_f32_f16 (inline zero accumulator) instead of the VOP2 v_dot2c form,
+# which needs a register copy per product.  amdgpu-mfma-vgpr-form: MFMA
+# accumulators in VGPRs (no accvgpr moves).
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Xclang", "-target-feature", "-Xclang", "-dot5-insts",
+          "-mllvm", "-amdgpu-mfma-vgpr-form"]
 HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 
 # (source, object name, extra defines, is_device)
@@ -56,7 +62,8 @@ def _compile(unit, force):
     cmd = [HIPCC] + (DEVICE if dev else HOST) + COMMON + defs + ["-c", srcp, "-o", objp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass does not know the packed-fp32-ops feature: harmless
-    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    err = "\n".join(l for l in r.stderr.splitlines()
+                     if "packed-fp32-ops" not in l and "dot5-insts" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{err}")
     return objp, err

@@ -2,6 +2,7 @@
 // host side of every entry point declared in include/bfpfft.h.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -63,9 +64,21 @@ int upload_twiddles(int log2n, int prec, void **out) {
   if ((int)t.size() != bfp::twiddle_entries(log2n))
     return fail(BFP_EINVAL, "internal: twiddle table size mismatch");
   const int fmt = tw_format(prec);
-  const size_t bytes = std::max<size_t>(16, t.size() * bfp_format_bytes(fmt));
+  size_t bytes = std::max<size_t>(16, t.size() * bfp_format_bytes(fmt));
   std::vector<unsigned char> host(bytes, 0);
   bfp::encode_complex(t.data(), t.size(), fmt, host.data());
+  if (bfp::has_mfma_engine(prec, log2n)) {
+    // matrix-core table (DFT16 operands + dot2-form twiddles) first, the
+    // vector-ALU engine's table after it at kMfmaTableBytes
+    std::vector<uint16_t> m = bfp::mfma4096_table();
+    std::vector<unsigned char> both((const unsigned char *)m.data(),
+                                    (const unsigned char *)m.data() + m.size() * sizeof(uint16_t));
+    if (both.size() != (size_t)bfp::kMfmaTableBytes)
+      return fail(BFP_EINVAL, "internal: matrix-core table size mismatch");
+    both.insert(both.end(), host.begin(), host.end());
+    host.swap(both);
+    bytes = host.size();
+  }
   void *d = nullptr;
   hipError_t e = hipMalloc(&d, bytes);
   if (e != hipSuccess) return fail(BFP_ENOMEM, "hipMalloc twiddles failed");
@@ -138,10 +151,14 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   a.out = out;
   a.rows = rows;
   a.tw = p->tw;
+  if (bfp::has_mfma_engine(p->prec, p->log2n) && p->tune_engine == 1)
+    a.tw = static_cast<const unsigned char *>(p->tw) + bfp::kMfmaTableBytes;
   a.filter = filter;
   a.phasor = phasor;
   a.flags = kflags(flags | p->flags);
   a.nonfinite = p->nonfinite;
+  a.grid_limit = p->tune_bpc > 0 ? p->tune_bpc * p->cu_count : 0;
+  a.engine = p->tune_engine;
   const bool out32 = ((flags | p->flags) & BFP_FLAG_OUT_FP32) != 0;
   int cur = 0;
   (void)hipGetDevice(&cur);
@@ -233,6 +250,11 @@ int fft_plan(bfp_plan *out, int n, int batch, int prec, unsigned flags) {
   p->prec = prec;
   p->flags = flags;
   (void)hipGetDevice(&p->device);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) p->cu_count = prop.multiProcessorCount;
+    if (p->cu_count <= 0) p->cu_count = 1;
+  }
   st = upload_twiddles(l, prec, &p->tw);
   if (st) {
     free_plan(p);
@@ -349,6 +371,15 @@ int sar_range_compress(bfp_plan range_plan, const void *echo, void *rc, const vo
                   stream);
 }
 
+int bfp_device_copy(const void *in, void *out, long long bytes, void *stream) {
+  if (bytes < 0 || (bytes % 16) != 0) return fail(BFP_EINVAL, "bytes must be a non-negative multiple of 16");
+  if (bytes == 0) return BFP_OK;
+  if (!in || !out) return fail(BFP_EINVAL, "NULL data pointer");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(BFP_EINVAL, "pointers must be 16-byte aligned");
+  hipError_t e = bfp::launch_copy(in, out, bytes, (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "copy launch");
+}
+
 int sar_corner_turn(const void *in, void *out, int rows, int cols, int fmt, void *stream) {
   if (rows < 0 || cols < 0) return fail(BFP_EINVAL, "negative size");
   if (rows == 0 || cols == 0) return BFP_OK;
@@ -429,6 +460,74 @@ int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, co
   e = bfp::launch_phase_grad(az_plan->prec == BFP_FP16_STORE_FP32_COMPUTE, az_plan->log2n, a,
                              stats != nullptr, (hipStream_t)stream);
   return e == hipSuccess ? BFP_OK : hip_fail(e, "phase gradient launch");
+}
+
+int fft_plan_set_tuning(bfp_plan p, int engine, int blocks_per_cu) {
+  if (!p) return fail(BFP_EINVAL, "plan is NULL");
+  if (engine < 0 || engine > 1) return fail(BFP_EINVAL, "engine must be 0 or 1");
+  if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(BFP_EINVAL, "blocks_per_cu must be in [0, 64]");
+  if (p->kind == 1) {
+    const int b = blocks_per_cu == 0 ? p->uneven_max_bpc : std::min(blocks_per_cu, p->uneven_max_bpc);
+    p->grid = b * p->cu_count;
+  }
+  p->tune_engine = engine;
+  p->tune_bpc = blocks_per_cu;
+  return BFP_OK;
+}
+
+int fft_plan_get_tuning(bfp_plan p, int *engine, int *blocks_per_cu) {
+  if (!p) return fail(BFP_EINVAL, "plan is NULL");
+  if (engine) *engine = p->tune_engine;
+  if (blocks_per_cu) *blocks_per_cu = p->tune_bpc;
+  return BFP_OK;
+}
+
+int fft_autotune(bfp_plan p, int op, const void *in, void *out, const void *filter, int reps,
+                 float *best_ms, void *stream) {
+  if (!p) return fail(BFP_EINVAL, "plan is NULL");
+  if (reps < 1 || reps > 10000) return fail(BFP_EINVAL, "reps must be in [1, 10000]");
+  if (p->kind == 0 && (op < 0 || op > 2)) return fail(BFP_EINVAL, "op must be 0, 1 or 2");
+  if (p->kind == 0 && op == 2 && !filter) return fail(BFP_EINVAL, "compression needs a filter");
+  std::vector<std::pair<int, int>> cands;
+  if (p->kind == 1) {
+    for (int b = 1; b <= p->uneven_max_bpc; ++b) cands.push_back({0, b});
+  } else {
+    const bool mf = bfp::has_mfma_engine(p->prec, p->log2n);
+    for (int e = 0; e <= (mf ? 1 : 0); ++e)
+      for (int b : {0, 1, 2, 4, 8}) cands.push_back({mf ? e : 1, b});
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(BFP_EHIP, "hipEventCreate failed");
+  auto call = [&]() -> int {
+    if (p->kind == 1) return fft_exec_uneven(p, in, out, stream);
+    if (op == 0) return fft_exec_fwd(p, in, out, stream);
+    if (op == 1) return fft_exec_inv_bfp(p, in, out, filter, stream);
+    return sar_range_compress(p, in, out, filter, p->batch, 0u, stream);
+  };
+  float best = 1e30f;
+  std::pair<int, int> pick = cands.front();
+  int st = BFP_OK;
+  for (auto &c : cands) {
+    if ((st = fft_plan_set_tuning(p, c.first, c.second))) break;
+    for (int w = 0; w < 2 && !st; ++w) st = call();
+    if (st) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && !st; ++r) st = call();
+    (void)hipEventRecord(e1, s);
+    if (st) break;
+    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(BFP_EHIP, "hipEventSynchronize"); break; }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    if (ms < best) { best = ms; pick = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if (best_ms) *best_ms = best;
+  return fft_plan_set_tuning(p, pick.first, pick.second);
 }
 
 /* uneven entry points are defined in uneven_api.cpp */

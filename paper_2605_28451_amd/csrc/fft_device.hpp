@@ -68,6 +68,15 @@ __device__ __forceinline__ h2 mul_m1mi(h2 a, float k) { return (h2{a.y, -a.x} - 
 __device__ __forceinline__ h2 mul_m1pi(h2 a, float k) { return (h2{-a.y, a.x} - a) * h2{(f16)k, (f16)k}; }
 __device__ __forceinline__ h2 mul_1pi(h2 a, float k) { return (a + h2{-a.y, a.x}) * h2{(f16)k, (f16)k}; }
 
+// conj(a) . s in one packed multiply by (s, -s); conj(a) as a sign flip of
+// the high half (one bit operation, for values that go straight to memory).
+__device__ __forceinline__ c32 conj_scale(c32 a, float s) { return c32{a.x * s, -(a.y * s)}; }
+__device__ __forceinline__ h2 conj_scale(h2 a, float s) { return a * h2{(f16)s, (f16)-s}; }
+__device__ __forceinline__ c32 conj_store(c32 a) { return c32{a.x, -a.y}; }
+__device__ __forceinline__ h2 conj_store(h2 a) {
+  return __builtin_bit_cast(h2, __builtin_bit_cast(uint32_t, a) ^ 0x80000000u);
+}
+
 // ------------------------------------------------- radix constants ------
 // cos(pi/4), cos(pi/8), sin(pi/8) to 20 significant digits.
 #define BFP_C8 0.70710678118654752440f
@@ -243,8 +252,8 @@ __device__ __forceinline__ uint32_t fp8_encode(float x) {
 
 struct ModeFP32 {
   typedef c32 Store; typedef c32 Lds; typedef c32 Comp; typedef c32 Tw; typedef c32 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, size_t i) { return p[i]; }
-  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) { p[i] = v; }
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return p[i]; }
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { p[i] = v; }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(v, w); }
@@ -254,8 +263,8 @@ struct ModeFP32 {
 
 struct ModeFP16 {  // pure packed FP16
   typedef h2 Store; typedef h2 Lds; typedef h2 Comp; typedef h2 Tw; typedef h2 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, size_t i) { return p[i]; }
-  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) { p[i] = v; }
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return p[i]; }
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { p[i] = v; }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(v, w); }
@@ -268,8 +277,8 @@ __device__ __forceinline__ h2 c32_to_h2(c32 v) { return h2{(f16)v.x, (f16)v.y}; 
 
 struct ModeF16StoreF32 {
   typedef h2 Store; typedef h2 Lds; typedef c32 Comp; typedef c32 Tw; typedef h2 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, size_t i) { return h2_to_c32(p[i]); }
-  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) { p[i] = c32_to_h2(v); }
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return h2_to_c32(p[i]); }
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { p[i] = c32_to_h2(v); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return c32_to_h2(v); }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return h2_to_c32(v); }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(h2_to_c32(v), w); }
@@ -287,8 +296,8 @@ __device__ __forceinline__ c32 cmul_dot2(h2 a, h2 b) {
 
 struct ModeF16MulF32Acc {
   typedef h2 Store; typedef h2 Lds; typedef c32 Comp; typedef h2 Tw; typedef h2 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, size_t i) { return h2_to_c32(p[i]); }
-  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) { p[i] = c32_to_h2(v); }
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return h2_to_c32(p[i]); }
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { p[i] = c32_to_h2(v); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return c32_to_h2(v); }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return h2_to_c32(v); }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul_dot2(v, w); }
@@ -299,11 +308,11 @@ struct ModeF16MulF32Acc {
 template <int MANT, int BIAS>
 struct ModeFP8 {
   typedef fp8x2 Store; typedef c32 Lds; typedef c32 Comp; typedef c32 Tw; typedef c32 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, size_t i) {
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) {
     fp8x2 b = p[i];
     return c32{fp8_decode<MANT, BIAS>(b.x), fp8_decode<MANT, BIAS>(b.y)};
   }
-  static __device__ __forceinline__ void store(Store *p, size_t i, Comp v) {
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) {
     p[i] = fp8x2{(uint8_t)fp8_encode<MANT, BIAS>(v.x), (uint8_t)fp8_encode<MANT, BIAS>(v.y)};
   }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }

@@ -59,7 +59,21 @@ struct Geometry {
   static constexpr int tw_entries() { return tw_offset(S::P); }
 };
 
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ __forceinline__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+
+// True when, for every butterfly j, lds_pad(base_j + r NS) equals
+// lds_pad(base_j) + r NS + (r NS) / 16, i.e. the low four bits of base_j
+// plus those of r NS never carry: then the R scattered writes of a
+// butterfly use one address register and compile-time offsets.
+template <int R, int NS>
+constexpr bool pad_splits() {
+  for (int j = 0; j < 4096; ++j) {
+    const int base = (j / NS) * NS * R + (j % NS);
+    for (int r = 0; r < R; ++r)
+      if (lds_pad(base + r * NS) != lds_pad(base) + r * NS + ((r * NS) >> 4)) return false;
+  }
+  return true;
+}
 
 template <class M, int LOG2N>
 struct Engine {
@@ -72,22 +86,8 @@ struct Engine {
 
   template <int R>
   static __device__ __forceinline__ void load_tw_row(const Tw *__restrict__ p, Tw (&w)[R]) {
-    static_assert((R * sizeof(Tw)) % 8 == 0, "twiddle row size");
-    if constexpr ((R * sizeof(Tw)) % 16 == 0) {
-      const uint4 *q = reinterpret_cast<const uint4 *>(p);
-      constexpr int nv = R * sizeof(Tw) / 16;
-      uint4 tmp[nv];
 #pragma unroll
-      for (int i = 0; i < nv; ++i) tmp[i] = q[i];
-      __builtin_memcpy(&w[0], &tmp[0], sizeof(tmp));
-    } else {
-      const uint2 *q = reinterpret_cast<const uint2 *>(p);
-      constexpr int nv = R * sizeof(Tw) / 8;
-      uint2 tmp[nv];
-#pragma unroll
-      for (int i = 0; i < nv; ++i) tmp[i] = q[i];
-      __builtin_memcpy(&w[0], &tmp[0], sizeof(tmp));
-    }
+    for (int r = 0; r < R; ++r) w[r] = p[r];
   }
 
   // One Stockham pass.  On entry v[e] holds this thread's inputs (pass 0)
@@ -126,13 +126,16 @@ struct Engine {
       for (int r = 0; r < R; ++r) v[b + B * r] = u[r];
     }
     if constexpr (!LAST) {
+      static_assert(pad_splits<R, NS>(), "padded offsets of a butterfly must not straddle a pad");
       __syncthreads();  // all reads of the previous contents are done
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         const int j = t + T * b;
-        const int base = (j / NS) * NS * R + (j & (NS - 1));
+        const int pbase = lds_pad((j / NS) * NS * R + (j & (NS - 1)));
+        // lds_pad(base + r NS) = lds_pad(base) + r NS + (r NS) / 16 (see pad_splits)
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = M::to_lds(v[b + B * r]);
+        for (int r = 0; r < R; ++r)
+          lds[pbase + r * NS + ((r * NS) >> 4)] = M::to_lds(v[b + B * r]);
       }
       __syncthreads();
     }

@@ -15,5 +15,6 @@ uint8_t f64_to_fp8_bits(double x, int mant, int bias);
 void encode_complex(const std::complex<double> *src, size_t count, int fmt, void *dst);
 std::vector<std::complex<double>> twiddle_table(int log2n, const int *radix, int passes);
 void host_fft(std::vector<std::complex<double>> &a);
+std::vector<uint16_t> mfma4096_table();
 
 }  // namespace bfp

@@ -26,7 +26,14 @@ struct RowArgs {
   const void *phasor;    // n FP32 pairs exp(i phi_m) or NULL (compress only)
   unsigned flags;        // KFlags
   unsigned long long *nonfinite;  // device counter
+  int grid_limit;        // > 0: persistent grid of at most this many workgroups
+  int engine;            // 0: matrix cores where available, 1: vector ALU only
 };
+
+// whether (mode, size) has a matrix-core engine
+inline bool has_mfma_engine(int mode, int log2n) { return mode == 3 && log2n == 12; }
+// bytes of the matrix-core table (operand slices + dot2-form twiddles)
+constexpr int kMfmaTableBytes = 2 * (1024 + 4 * (256 + 4096));
 
 // Launch a row kernel; returns hipSuccess or the launch error.
 hipError_t launch_rows(int mode, int log2n, int op, bool out32, const RowArgs &a,
@@ -64,6 +71,9 @@ hipError_t launch_convert(const void *in, int in_fmt, void *out, int out_fmt, lo
 // Corner turn (transpose) of a rows x cols matrix of elements of `bytes`.
 hipError_t launch_transpose(const void *in, void *out, int rows, int cols, int bytes,
                             hipStream_t stream);
+
+// 16-byte-per-lane device copy of `bytes` (a multiple of 16).
+hipError_t launch_copy(const void *in, void *out, long long bytes, hipStream_t stream);
 
 // exp(i phi) table (FP32 pairs) from FP32 radians.
 hipError_t launch_phasor(const float *phase, void *phasor, int n, int negate,

@@ -27,6 +27,11 @@ struct bfp_plan_s {
   unsigned *queue = nullptr;
   int *order_d = nullptr;
   int grid = 0;
+  // tuning knobs (fft_plan_set_tuning / fft_autotune)
+  int tune_engine = 0;     // 0: matrix cores where available, 1: vector ALU only
+  int tune_bpc = 0;        // workgroups per CU of a persistent grid, 0 = default
+  int cu_count = 0;
+  int uneven_max_bpc = 1;
   // autofocus workspace
   void *tw32 = nullptr;          // FP32 twiddles (owned only when tw is FP16)
   double *ent_partial = nullptr; // kEntropyBlocks x 2 doubles

@@ -131,4 +131,24 @@ hipError_t launch_phasor(const float *phase, void *phasor, int n, int negate, hi
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------- copy ------
+// Plain streaming copy, 16 bytes per lane per iteration: the reference for
+// achievable HBM bandwidth and for calibrating memory counters.
+__global__ void __launch_bounds__(256) copy_kernel(const uint4 *__restrict__ in,
+                                                   uint4 *__restrict__ out, long long n16) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    out[i] = in[i];
+}
+
+hipError_t launch_copy(const void *in, void *out, long long bytes, hipStream_t s) {
+  const long long n16 = bytes / 16;
+  if (n16 <= 0) return hipSuccess;
+  long long blocks = (n16 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<const uint4 *>(in), static_cast<uint4 *>(out), n16);
+  return hipGetLastError();
+}
+
 }  // namespace bfp

@@ -129,8 +129,11 @@ int fft_plan_uneven(bfp_plan *out, int count, const int *log2n, const unsigned c
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, p->device) != hipSuccess)
       st = bfp::set_error(BFP_EHIP, "hipGetDeviceProperties failed");
-    else
-      p->grid = prop.multiProcessorCount * bfp::uneven_blocks_per_cu(prec);
+    else {
+      p->cu_count = prop.multiProcessorCount;
+      p->uneven_max_bpc = bfp::uneven_blocks_per_cu(prec);
+      p->grid = p->cu_count * p->uneven_max_bpc;
+    }
   }
   if (st) {
     fft_destroy(p);

@@ -1,4 +1,4 @@
-"""Quality metrics applied identically to oracle and GPU outputs (test infrastructure).
+"""Image-quality metrics, applied identically to oracle and GPU outputs.
 
 * ``sqnr_db`` -- 10 log10(sum|ref|^2 / sum|ref - a*out|^2), pooled over every
   element.  ``align=True`` uses the optimal real scale a* = Re<out,ref>/|out|^2,

@@ -173,6 +173,7 @@ def _fp8_encode_real(v: np.ndarray, fmt: str) -> np.ndarray:
     with np.errstate(divide="ignore"):
         e = np.floor(np.log2(np.where(a > 0, a, 1.0))).astype(np.int64)
     e = np.maximum(e, emin)
+    a = np.where(np.isnan(a), 0.0, a)
     q = np.rint(np.ldexp(a, (mant - e)))  # significand in units of the quantum
     # rounding may carry into the next binade
     carry = q >= (2 << mant)
@@ -184,6 +185,7 @@ def _fp8_encode_real(v: np.ndarray, fmt: str) -> np.ndarray:
     mf = np.where(normal, q - (1 << mant), q)
     bits = (ef << mant) | mf
     bits = np.where(a == 0, 0, bits)
+    bits = np.where(np.isnan(v), 0x7F, bits)  # NaN stays NaN (both formats)
     return (bits | (sign.astype(np.int64) << 7)).astype(np.uint8)
 
 
@@ -222,7 +224,10 @@ def decode(a: np.ndarray, fmt: str) -> np.ndarray:
         a = _fp8_decode_real(a, fmt)
     else:
         raise ValueError(fmt)
-    return a[..., 0] + 1j * a[..., 1]
+    out = np.empty(a.shape[:-1], dtype=np.complex128)
+    out.real = a[..., 0]
+    out.imag = a[..., 1]
+    return out
 
 
 def quantize(x: np.ndarray, fmt: str) -> np.ndarray:

@@ -4,7 +4,7 @@ import pytest
 import torch
 
 import oracle
-from oracle.metrics import sqnr_db
+from paper_2605_28451_amd.metrics import sqnr_db
 from paper_2605_28451_amd import api, scenes
 
 MODES = ["fp32", "fp16", "fp16_fp32", "fp16_mul_fp32_acc", "e4m3", "e5m2"]

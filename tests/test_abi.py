@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+declared in include/bfpfft.h, and its host-only entry points (table
+generation, validation, error strings) behave; no GPU compute is called."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_28451_amd import _lib, api, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfpfft.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char|double)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    lib = _lib.load()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in bfpfft.h but not exported"
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def test_host_only_queries():
+    lib = _lib.load()
+    assert [lib.bfp_storage_bytes(p) for p in range(6)] == [8, 4, 4, 4, 2, 2]
+    assert lib.bfp_storage_bytes(7) == -1
+    assert [lib.bfp_format_bytes(f) for f in range(4)] == [8, 4, 2, 2]
+    assert [lib.bfp_filter_format(p) for p in range(6)] == [0, 1, 1, 1, 0, 0]
+    assert lib.bfp_status_string(0) == b"ok"
+    assert lib.bfp_status_string(_lib.EINVAL) == b"invalid argument"
+
+
+def test_plan_validation_before_device_use():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.fft_plan(ctypes.byref(h), 1000, 1, 1, 0) == _lib.EINVAL
+    assert b"power of two" in lib.bfp_last_error()
+    assert lib.fft_plan(ctypes.byref(h), 4096, -1, 1, 0) == _lib.EINVAL
+    assert lib.fft_plan(ctypes.byref(h), 4096, 1, 9, 0) == _lib.EINVAL
+    assert lib.fft_plan(ctypes.byref(h), 4096, 1, 1, 1 << 20) == _lib.EINVAL
+    assert lib.fft_exec_fwd(None, None, None, None) == _lib.EINVAL
+    assert lib.fft_destroy(None) == _lib.EINVAL
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "fp32", "e4m3"])
+def test_host_filter_tables_match_oracle(fmt):
+    # A1: FP64 host tables rounded once; compare with the oracle's filter
+    # rounded by the independent numpy encoder
+    sc = scenes.range_scene(seed=2, n_pulses=1)
+    got = scenes.decode(api.make_filter(sc.replica, 4096, fmt), fmt)
+    want = scenes.quantize(oracle.matched_filter(sc.replica, 4096), fmt)
+    assert np.mean(got == want) > 0.999
+    ulp = {"fp16": 2.0 ** -11, "fp32": 2.0 ** -24, "e4m3": 2.0 ** -4}[fmt]
+    assert np.max(np.abs(got - want)) <= 2 * ulp
+    az = scenes.azimuth_replica_centred(4096, 512)
+    got = scenes.decode(api.make_filter(az, 4096, fmt), fmt)
+    want = scenes.quantize(oracle.matched_filter(az, 4096), fmt)
+    assert np.mean(got == want) > 0.999
+
+
+def test_make_filter_rejects_bad_sizes():
+    with pytest.raises(_lib.BfpError):
+        api.make_filter(np.ones(10), 1000, "fp16")
+    with pytest.raises(_lib.BfpError):
+        api.make_filter(np.ones(20), 16, "fp16")
+    with pytest.raises(_lib.BfpError):
+        api.make_filter(np.zeros(8), 16, "fp16")

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import oracle
-from oracle.metrics import sqnr_db
+from paper_2605_28451_amd.metrics import sqnr_db
 from paper_2605_28451_amd import api, scenes
 from tests.gpu_util import (FP16_MODES, FWD_SQNR_MIN, MODES, announce, download, need_gpu,
                             rand_rows, upload)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import metrics
+from paper_2605_28451_amd import metrics
 from paper_2605_28451_amd import scenes
 
 

@@ -1,0 +1,75 @@
+"""Tuning knobs and the autotuner (GPU tier): results do not depend on the
+persistent-grid size; both engines of the FP16-multiply mode meet the parity
+bar; the autotuner stores and reuses its choice."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_28451_amd import api, autotune, scenes
+from paper_2605_28451_amd.metrics import sqnr_db
+from tests.gpu_util import announce, download, need_gpu, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("mode,n", [("fp16", 4096), ("fp16_mul_fp32_acc", 4096), ("fp32", 1024)])
+def test_grid_size_does_not_change_results(mode, n):
+    need_gpu()
+    announce(f"tuning grid mode={mode} n={n}")
+    fmt = api.storage_format(mode)
+    rows = 300
+    sc = scenes.range_scene(seed=2, n_pulses=rows, n=n, length=n // 4)
+    x = upload(scenes.quantize(sc.echo, fmt), fmt)
+    H = api.filter_tensor(sc.replica, n, mode)
+    plan = api.FFTPlan(n, rows, mode)
+    ref_f = plan.forward(x).clone()
+    ref_c = plan.range_compress(x, H).clone()
+    for bpc in (1, 2, 8):
+        plan.set_tuning(0, bpc)
+        assert plan.get_tuning() == (0, bpc)
+        assert torch.equal(plan.forward(x), ref_f)
+        assert torch.equal(plan.range_compress(x, H), ref_c)
+
+
+def test_both_engines_meet_parity():
+    need_gpu()
+    x = scenes.quantize(scenes.gaussian_rows(1, 64, 4096), "fp16")
+    plan = api.FFTPlan(4096, 64, "fp16_mul_fp32_acc")
+    for engine in (0, 1):
+        plan.set_tuning(engine, 0)
+        X = download(plan.forward(upload(x, "fp16")), "fp16")
+        s = sqnr_db(oracle.fft(x), X)
+        print(f"engine={engine} SQNR {s:.2f} dB")
+        assert s >= 60.0
+
+
+def test_autotune_and_cache(tmp_path, monkeypatch):
+    need_gpu()
+    monkeypatch.setenv("BFP_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    x = upload(scenes.quantize(scenes.gaussian_rows(1, 512, 4096), "fp16"), "fp16")
+    out = torch.empty_like(x)
+    plan = api.FFTPlan(4096, 512, "fp16_mul_fp32_acc")
+    e = autotune.tune(plan, "forward", x, out, reps=5)
+    assert e["ms"] > 0 and e["engine"] in (0, 1) and e["blocks_per_cu"] in (0, 1, 2, 4, 8)
+    plan2 = api.FFTPlan(4096, 512, "fp16_mul_fp32_acc")
+    assert autotune.apply_cached(plan2, "forward")
+    assert plan2.get_tuning() == (e["engine"], e["blocks_per_cu"])
+    # tuned plan still correct
+    X = download(plan2.forward(x), "fp16")
+    xq = scenes.decode(x.cpu().numpy(), "fp16")
+    assert sqnr_db(oracle.fft(xq), X) >= 60.0
+
+
+def test_uneven_grid_size_does_not_change_results():
+    need_gpu()
+    ub = scenes.uneven_batch(seed=4, count=500)
+    x = upload(scenes.quantize(ub.x, "fp16"), "fp16")
+    plan = api.UnevenPlan(ub.log2n, ub.inverse, "fp16")
+    ref = plan.execute(x).clone()
+    for bpc in (1, 2):
+        plan.set_tuning(0, bpc)
+        assert torch.equal(plan.execute(x), ref)
+    ms = plan.autotune_on(0, x, torch.empty_like(x), reps=3)
+    assert ms > 0
+    assert torch.equal(plan.execute(x), ref)

@@ -4,7 +4,7 @@ import pytest
 import torch
 
 import oracle
-from oracle.metrics import sqnr_db
+from paper_2605_28451_amd.metrics import sqnr_db
 from paper_2605_28451_amd import api, scenes
 from tests.gpu_util import FWD_SQNR_MIN, announce, download, need_gpu, upload
 
