@@ -133,7 +133,6 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
   typedef Geometry<LOG2N> G;
   typedef Engine<ModeFP32, LOG2N> EN;
   constexpr int E = G::E, T = G::T, N = G::N;
-  constexpr float inv_n = 1.0f / (float)N;
   __shared__ c32 lds_all[G::TPW * G::LDS_N];
   const int local = threadIdx.x / T;
   const int t = threadIdx.x & (T - 1);
@@ -166,7 +165,7 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const c32 h = load_any<StoreT>(flt, t + T * e);
-      v[e] = cscale(cconj(cmul(v[e], cconj(h))), inv_n);  // adjoint: conj(H_a)
+      v[e] = conj_pow2<LOG2N>(cmul(v[e], cconj(h)));  // adjoint: conj(H_a), then the block shift
     }
     EN::run(v, lds, tw, t);
     if (active) {

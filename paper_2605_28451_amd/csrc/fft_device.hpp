@@ -68,10 +68,34 @@ __device__ __forceinline__ h2 mul_m1mi(h2 a, float k) { return (h2{a.y, -a.x} - 
 __device__ __forceinline__ h2 mul_m1pi(h2 a, float k) { return (h2{-a.y, a.x} - a) * h2{(f16)k, (f16)k}; }
 __device__ __forceinline__ h2 mul_1pi(h2 a, float k) { return (a + h2{-a.y, a.x}) * h2{(f16)k, (f16)k}; }
 
-// conj(a) . s in one packed multiply by (s, -s); conj(a) as a sign flip of
-// the high half (one bit operation, for values that go straight to memory).
-__device__ __forceinline__ c32 conj_scale(c32 a, float s) { return c32{a.x * s, -(a.y * s)}; }
-__device__ __forceinline__ h2 conj_scale(h2 a, float s) { return a * h2{(f16)s, (f16)-s}; }
+// Exact power-of-two scaling a . 2^-K (the block-floating-point shift) as an
+// ldexp instruction: exact for normal results, round-to-nearest-even into
+// subnormals, and never contracted into a neighbouring FMA, so the shifted
+// value is the same in every kernel.
+__device__ __forceinline__ f16 ldexp16(f16 v, int k) {
+  return (f16)__builtin_amdgcn_ldexph((__fp16)v, k);
+}
+template <int K>
+__device__ __forceinline__ c32 pow2(c32 a) {
+  if constexpr (K == 0) return a;
+  else return c32{__builtin_ldexpf(a.x, -K), __builtin_ldexpf(a.y, -K)};
+}
+template <int K>
+__device__ __forceinline__ h2 pow2(h2 a) {
+  if constexpr (K == 0) return a;
+  else return h2{ldexp16(a.x, -K), ldexp16(a.y, -K)};
+}
+// conj(a) . 2^-K
+template <int K>
+__device__ __forceinline__ c32 conj_pow2(c32 a) {
+  if constexpr (K == 0) return c32{a.x, -a.y};
+  else return c32{__builtin_ldexpf(a.x, -K), -__builtin_ldexpf(a.y, -K)};
+}
+template <int K>
+__device__ __forceinline__ h2 conj_pow2(h2 a) {
+  if constexpr (K == 0) return h2{a.x, -a.y};
+  else return h2{ldexp16(a.x, -K), (f16)-ldexp16(a.y, -K)};
+}
 __device__ __forceinline__ c32 conj_store(c32 a) { return c32{a.x, -a.y}; }
 __device__ __forceinline__ h2 conj_store(h2 a) {
   return __builtin_bit_cast(h2, __builtin_bit_cast(uint32_t, a) ^ 0x80000000u);

@@ -84,18 +84,33 @@ struct Engine {
   static constexpr int E = G::E;
   static constexpr int T = G::T;
 
-  template <int R>
-  static __device__ __forceinline__ void load_tw_row(const Tw *__restrict__ p, Tw (&w)[R]) {
+  // Twiddle rows of pass PASS for this thread: butterfly b uses row
+  // (t + T b) mod NS, entries r = 0..R-1, kept at w[b R + r].
+  template <int PASS>
+  static __device__ __forceinline__ void load_tw(const Tw *__restrict__ tw, int t, Tw (&w)[E]) {
+    if constexpr (PASS > 0 && PASS < G::S::P) {
+      constexpr int R = G::radix(PASS);
+      constexpr int NS = G::span(PASS);
+      constexpr int B = E / R;
+      const Tw *twp = tw + G::tw_offset(PASS);
 #pragma unroll
-    for (int r = 0; r < R; ++r) w[r] = p[r];
+      for (int b = 0; b < B; ++b) {
+        const Tw *row = twp + ((t + T * b) & (NS - 1)) * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r) w[b * R + r] = row[r];
+      }
+    }
   }
 
   // One Stockham pass.  On entry v[e] holds this thread's inputs (pass 0)
-  // or nothing (later passes, which read LDS); on exit v[e] holds the
-  // outputs (last pass) or the outputs have been written to LDS.
+  // or nothing (later passes, which read LDS), and w this pass's twiddle
+  // rows; the next pass's rows are loaded into w as soon as this pass has
+  // consumed its own, so their latency overlaps the butterflies and the LDS
+  // exchange.  On exit v[e] holds the outputs (last pass) or the outputs
+  // have been written to LDS.
   template <int PASS>
   static __device__ __forceinline__ void pass(Comp (&v)[E], Lds *lds, const Tw *__restrict__ tw,
-                                              int t) {
+                                              int t, Tw (&w)[E]) {
     constexpr int R = G::radix(PASS);
     constexpr int NS = G::span(PASS);
     constexpr int B = E / R;
@@ -104,18 +119,14 @@ struct Engine {
       Lds raw[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) raw[e] = lds[lds_pad(t + T * e)];
-      const Tw *twp = tw + G::tw_offset(PASS);
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        const int j = t + T * b;
-        const int m = j & (NS - 1);
-        Tw w[R];
-        load_tw_row<R>(twp + m * R, w);
         v[b] = M::from_lds(raw[b]);
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[b + B * r] = M::twiddle(raw[b + B * r], w[r]);
+        for (int r = 1; r < R; ++r) v[b + B * r] = M::twiddle(raw[b + B * r], w[b * R + r]);
       }
     }
+    load_tw<PASS + 1>(tw, t, w);
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       Comp u[R];
@@ -144,10 +155,12 @@ struct Engine {
   // Full forward transform: v[e] = x[t + T e] in, v[e] = X[t + T e] out.
   static __device__ __forceinline__ void run(Comp (&v)[E], Lds *lds, const Tw *__restrict__ tw,
                                              int t) {
-    pass<0>(v, lds, tw, t);
-    if constexpr (G::S::P > 1) pass<1>(v, lds, tw, t);
-    if constexpr (G::S::P > 2) pass<2>(v, lds, tw, t);
-    if constexpr (G::S::P > 3) pass<3>(v, lds, tw, t);
+    Tw w[E];
+    load_tw<1>(tw, t, w);
+    pass<0>(v, lds, tw, t, w);
+    if constexpr (G::S::P > 1) pass<1>(v, lds, tw, t, w);
+    if constexpr (G::S::P > 2) pass<2>(v, lds, tw, t, w);
+    if constexpr (G::S::P > 3) pass<3>(v, lds, tw, t, w);
   }
 };
 

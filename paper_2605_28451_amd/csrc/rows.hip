@@ -57,7 +57,6 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   typedef typename M::Filt Filt;
   typedef typename M::Tw Tw;
   constexpr int E = G::E, T = G::T, N = G::N;
-  constexpr float inv_n = 1.0f / (float)N;  // 2^-LOG2N, exact
   constexpr bool naive = (V & V_NAIVE) != 0;
   constexpr bool conj_f = (V & V_CONJ) != 0;
   constexpr bool phasor = (V & V_PHASOR) != 0;
@@ -77,9 +76,10 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
 
   Comp v[E];
   if (active) {
-    const Store *src = static_cast<const Store *>(a.in) + row * N;
+    // one per-thread base, element offsets T e as immediates
+    const Store *src = static_cast<const Store *>(a.in) + row * N + t;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = M::load(src, t + (unsigned)(T * e));
+    for (int e = 0; e < E; ++e) v[e] = M::load(src, (unsigned)(T * e));
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = Comp{};
@@ -90,30 +90,31 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   } else {
     if constexpr (OP == OP_COMPRESS) {
       if constexpr (phasor) {
-        const c32 *ph = static_cast<const c32 *>(a.phasor);
+        const c32 *ph = static_cast<const c32 *>(a.phasor) + t;
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = mul_c32(v[e], ph[t + T * e]);
+        for (int e = 0; e < E; ++e) v[e] = mul_c32(v[e], ph[T * e]);
       }
       EN::run(v, lds, tw, t);
     }
     // BFP fold at the inverse's load: conj(z . H) . 2^-log2N, or with the
     // conjugated filter conj(z . conj H) = conj(z) . H
-    constexpr float pre = naive ? 1.0f : inv_n;  // exact power of two
+    constexpr int K = naive ? 0 : LOG2N;  // block shift 2^-log2N
     const Filt *f = static_cast<const Filt *>(a.filter);
     if (f) {
+      const Filt *ft = f + t;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const Filt h = f[t + T * e];
-        v[e] = conj_f ? cscale(M::fmul(cconj(v[e]), h), pre) : conj_scale(M::fmul(v[e], h), pre);
+        const Filt h = ft[T * e];
+        v[e] = conj_f ? pow2<K>(M::fmul(cconj(v[e]), h)) : conj_pow2<K>(M::fmul(v[e], h));
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = conj_scale(v[e], pre);
+      for (int e = 0; e < E; ++e) v[e] = conj_pow2<K>(v[e]);
     }
     EN::run(v, lds, tw, t);
     if constexpr (naive) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = cscale(M::round_store(cconj(v[e])), inv_n);
+      for (int e = 0; e < E; ++e) v[e] = pow2<LOG2N>(M::round_store(cconj(v[e])));
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = conj_store(v[e]);
@@ -122,13 +123,13 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
 
   if (active) {
     if constexpr (OUT32) {
-      c32 *dst = static_cast<c32 *>(a.out) + row * N;
+      c32 *dst = static_cast<c32 *>(a.out) + row * N + t;
 #pragma unroll
-      for (int e = 0; e < E; ++e) dst[t + (unsigned)(T * e)] = to_c32(v[e]);
+      for (int e = 0; e < E; ++e) dst[(unsigned)(T * e)] = to_c32(v[e]);
     } else {
-      Store *dst = static_cast<Store *>(a.out) + row * N;
+      Store *dst = static_cast<Store *>(a.out) + row * N + t;
 #pragma unroll
-      for (int e = 0; e < E; ++e) M::store(dst, t + (unsigned)(T * e), v[e]);
+      for (int e = 0; e < E; ++e) M::store(dst, (unsigned)(T * e), v[e]);
     }
     if (a.flags & KF_CHECK_FINITE) {
       unsigned bad = 0;
@@ -156,7 +157,6 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
 template <int OP, int V, bool OUT32>
 __global__ void __launch_bounds__(256) row_kernel_mfma(RowArgs a) {
   constexpr int N = 4096;
-  constexpr float inv_n = 1.0f / (float)N;
   constexpr bool naive = (V & V_NAIVE) != 0;
   constexpr bool conj_f = (V & V_CONJ) != 0;
   constexpr bool phasor = (V & V_PHASOR) != 0;
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256) row_kernel_mfma(RowArgs a) {
       for (int k = 0; k < 16; ++k) y[k] = h2_to_c32(x[k]);
     }
     // BFP fold: conj(z . H) . 2^-12 (exact), FP16 operands, FP32 sums
-    constexpr float pre = naive ? 1.0f : inv_n;
+    constexpr int K = naive ? 0 : 12;  // block shift 2^-12
     const h2 *f = static_cast<const h2 *>(a.filter);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -198,16 +198,16 @@ __global__ void __launch_bounds__(256) row_kernel_mfma(RowArgs a) {
         if (f) {
           const h2 h = f[E.pos(m, i)];
           if constexpr (conj_f) {
-            const h2 xa = h2{(f16)y[k].x, (f16)y[k].y}, xb = h2{(f16)(-y[k].y), (f16)y[k].x};
-            z = c32{__builtin_amdgcn_fdot2(xa, h, 0.0f, false) * pre,
-                    __builtin_amdgcn_fdot2(xb, h, 0.0f, false) * pre};
+            const h2 xa = c32_to_h2(c32{y[k].x, y[k].y}), xb = c32_to_h2(c32{-y[k].y, y[k].x});
+            z = pow2<K>(c32{__builtin_amdgcn_fdot2(xa, h, 0.0f, false),
+                            __builtin_amdgcn_fdot2(xb, h, 0.0f, false)});
           } else {
-            const h2 xa = h2{(f16)y[k].x, (f16)(-y[k].y)}, xb = h2{(f16)y[k].y, (f16)y[k].x};
-            z = c32{__builtin_amdgcn_fdot2(xa, h, 0.0f, false) * pre,
-                    -(__builtin_amdgcn_fdot2(xb, h, 0.0f, false) * pre)};
+            const h2 xa = c32_to_h2(c32{y[k].x, -y[k].y}), xb = c32_to_h2(c32{y[k].y, y[k].x});
+            z = conj_pow2<K>(c32{__builtin_amdgcn_fdot2(xa, h, 0.0f, false),
+                                 __builtin_amdgcn_fdot2(xb, h, 0.0f, false)});
           }
         } else {
-          z = conj_scale(y[k], pre);
+          z = conj_pow2<K>(y[k]);
         }
         x[k] = c32_to_h2(z);
       }
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(256) row_kernel_mfma(RowArgs a) {
   if constexpr (OP != OP_FWD) {
 #pragma unroll
     for (int k = 0; k < 16; ++k)
-      y[k] = naive ? cscale(h2_to_c32(c32_to_h2(cconj(y[k]))), inv_n) : cconj(y[k]);
+      y[k] = naive ? pow2<12>(h2_to_c32(c32_to_h2(cconj(y[k])))) : cconj(y[k]);
   }
 
   if constexpr (OUT32) {

@@ -43,9 +43,8 @@ __device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typenam
   typedef Engine<M, LOG2N> EN;
   typedef typename M::Comp Comp;
   typedef typename M::Store Store;
-  constexpr int E = G::E, T = G::T, N = G::N;
+  constexpr int E = G::E, T = G::T;
   static_assert((UNEVEN_WG / T) * G::LDS_N <= UNEVEN_LDS, "item exceeds LDS");
-  constexpr float inv_n = 1.0f / (float)N;
   const int local = threadIdx.x / T;
   const int t = threadIdx.x & (T - 1);
   const bool active = local < d.y;
@@ -62,7 +61,7 @@ __device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typenam
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       Comp z = M::load(src, t + T * e);
-      v[e] = inv ? cscale(cconj(z), inv_n) : z;  // BFP fold for inverse transforms
+      v[e] = inv ? conj_pow2<LOG2N>(z) : z;  // BFP fold for inverse transforms
     }
   } else {
 #pragma unroll

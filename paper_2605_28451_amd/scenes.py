@@ -197,6 +197,10 @@ def _fp8_decode_real(b: np.ndarray, fmt: str) -> np.ndarray:
     mf = b & ((1 << mant) - 1)
     val = np.where(ef == 0, np.ldexp(mf.astype(np.float64), 1 - bias - mant),
                    np.ldexp((mf + (1 << mant)).astype(np.float64), (ef - bias - mant)))
+    if fmt == "e4m3":  # S.1111.111 is NaN; no infinities
+        val = np.where((ef == 15) & (mf == 7), np.nan, val)
+    else:              # exponent 31: infinity (mantissa 0) or NaN
+        val = np.where(ef == 31, np.where(mf == 0, np.inf, np.nan), val)
     return s * val
 
 

@@ -86,9 +86,15 @@ def test_convert_matches_host_encoder(src, dst):
         x.imag = scenes.decode(scenes.encode(v[2500:].astype(complex), src), src).real
     with np.errstate(over="ignore", invalid="ignore"):
         want = scenes.encode(x, dst)
-    got = api.convert(upload(x, src), src, dst)
-    torch.cuda.synchronize()
-    assert np.array_equal(got.cpu().numpy(), want)
+    got = api.convert(upload(x, src), src, dst).cpu().numpy()
+    # bitwise for every non-NaN value; NaN stays NaN (payload bits may differ)
+    dg, dw = scenes.decode(got, dst), scenes.decode(want, dst)
+    for part in ("real", "imag"):
+        a, b = getattr(dg, part), getattr(dw, part)
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+    comp_nan = np.stack([np.isnan(dw.real), np.isnan(dw.imag)], -1)
+    assert np.array_equal(np.where(comp_nan, 0, got), np.where(comp_nan, 0, want))
+    assert comp_nan.any()
 
 
 def _gpu_frame(sc, mode, phase=None):

@@ -28,6 +28,10 @@ def test_fp8_encoder_matches_torch_and_emulator(fmt, tdtype):
     dec = scenes.decode(np.stack([enc, enc], -1), fmt).real
     assert np.array_equal(dec, emulator.round_to_format(v, fmt))
     assert np.array_equal(dec, t.to(torch.float64).numpy())
+    # NaN encodings decode to NaN, and NaN encodes to NaN
+    nan_code = scenes.encode(np.array([complex(np.nan, 1.0)]), fmt)
+    assert np.isnan(scenes.decode(nan_code, fmt).real[0])
+    assert np.isnan(torch.from_numpy(nan_code[..., 0].copy()).view(tdtype).to(torch.float32).numpy()[0])
 
 
 def test_fp16_fp32_encoders_round_nearest_even():
