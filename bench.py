@@ -43,20 +43,98 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "range_compress_2048x4096_traffic.
 def measured_traffic(mode):
     """HBM bytes per launch of the fused compression from the committed PMC
     summary, or None when the kernel sources changed since it was taken."""
-    import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    for name in rec.get("kernel_sources", []):
-        with open(os.path.join(ROOT, "paper_2605_28451_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != rec.get("kernel_source_sha256"):
+    if rec.get("kernel_sources") != KERNEL_SOURCES or \
+            kernel_source_sha256() != rec.get("kernel_source_sha256"):
         return None
     m = rec.get("modes", {}).get(mode)
     return None if m is None else m["traffic_bytes"]
+
+
+KERNEL_SOURCES = ["rows.hip", "fft_engine.hpp", "fft_device.hpp", "fft_mfma.hpp", "internal.hpp"]
+
+
+def kernel_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_28451_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_summary(specs):
+    """Turn rocprofv3 --pmc databases of `bench.py --kernel-only <mode>` runs
+    into the committed traffic record.  specs: [(mode, fetch_dir, write_dir)],
+    each dir holding one run with FETCH_SIZE resp. WRITE_SIZE.  Per counter
+    the kernel's mean KiB per dispatch is scaled by known bytes / KiB of the
+    device copy that the same run performs (32 MiB read + 32 MiB written)."""
+    import glob
+    import sqlite3
+
+    def means(d):
+        dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+        if len(dbs) != 1:
+            raise SystemExit(f"expected one rocprofv3 database under {d}, found {len(dbs)}")
+        con = sqlite3.connect(dbs[0])
+        rows = con.execute("select kernel_name, value from counters_collection").fetchall()
+        agg = {}
+        for name, v in rows:
+            agg.setdefault(name, []).append(float(v))
+        kern = [k for k in agg if "bfp::row_kernel" in k]
+        copy = [k for k in agg if "bfp::copy_kernel" in k]
+        if not kern or len(copy) != 1:
+            raise SystemExit(f"no row kernel / copy kernel dispatches in {dbs[0]}")
+        k = max(kern, key=lambda n: len(agg[n]))
+        return k, sum(agg[k]) / len(agg[k]), sum(agg[copy[0]]) / len(agg[copy[0]])
+
+    copy_kib = 32 * 1024  # the copy moves 32 MiB each way
+    rec = {"workload": "fused range compression, 2048 x 4096, FP16 storage",
+           "source": "profiles/range_compress_2048x4096_hbm_traffic.md",
+           "kernel_sources": KERNEL_SOURCES, "kernel_source_sha256": kernel_source_sha256(),
+           "modes": {}}
+    lines = ["| mode | kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | copy FETCH / WRITE KiB |",
+             "|---|---|---|---|---|"]
+    algo = 2 * 2048 * 4096 * 4
+    notes = []
+    for mode, fdir, wdir in specs:
+        kf, f_kib, cf = means(fdir)
+        kw, w_kib, cw = means(wdir)
+        ff, fw = copy_kib / cf, copy_kib / cw
+        traffic = int(round(f_kib * ff * 1024 + w_kib * fw * 1024))
+        rec["modes"][mode] = {"traffic_bytes": traffic, "fetch_factor": round(ff, 4),
+                              "write_factor": round(fw, 4), "kernel": kf}
+        lines.append(f"| {mode} | `{kf[:70]}` | {f_kib:.1f} | {w_kib:.1f} | {cf:.1f} / {cw:.1f} |")
+        notes.append(f"- {mode}: fetch {f_kib:.0f} KiB x {ff:.3f} + write {w_kib:.0f} KiB x {fw:.3f} = "
+                     f"{traffic} B ({traffic / algo:.3f} x algorithmic {algo} B)")
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print("\n".join(lines + [""] + notes))
+
+
+def trace_summary(d, top=12):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (its database)."""
+    import glob
+    import sqlite3
+    dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+    if len(dbs) != 1:
+        raise SystemExit(f"expected one rocprofv3 database under {d}, found {len(dbs)}")
+    con = sqlite3.connect(dbs[0])
+    rows = con.execute("select name, count(*), sum(duration), avg(duration), min(duration), "
+                       "max(duration) from kernels group by name order by sum(duration) desc").fetchall()
+    total = sum(r[2] for r in rows) or 1
+    out = ["| kernel | calls | average us | min us | max us | share of GPU time |",
+           "|---|---|---|---|---|---|"]
+    for name, n, tot, avg, mn, mx in rows[:top]:
+        name = name if len(name) <= 90 else name[:87] + "..."
+        out.append(f"| `{name}` | {n} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | {mx / 1e3:.2f} | "
+                   f"{100.0 * tot / total:.1f}% |")
+    print("\n".join(out))
 
 
 def fft_flops(n, transforms):
@@ -65,23 +143,23 @@ def fft_flops(n, transforms):
 
 
 def time_launches(launch, n_sets, steps, warmup):
-    """Run `launch(i)` (one kernel launch on the current stream) for warmup
-    + steps iterations rotating over n_sets buffer sets; return per-launch
-    durations (ms) of the timed steps and the total timed wall (ms)."""
+    """Run `launch(i)` (kernel launches on the current stream) for warmup +
+    steps iterations rotating over n_sets buffer sets.  The timed steps are
+    issued back to back between one pair of events on that stream; returns
+    (average ms per step, total timed ms)."""
     import torch
     for i in range(warmup):
         launch(i % n_sets)
     torch.cuda.synchronize()
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
     for i in range(steps):
-        ev0[i].record()
         launch(i % n_sets)
-        ev1[i].record()
+    ev1.record()
     torch.cuda.synchronize()
-    per = [ev0[i].elapsed_time(ev1[i]) for i in range(steps)]
-    total = ev0[0].elapsed_time(ev1[steps - 1])
-    return per, total
+    total = ev0.elapsed_time(ev1)
+    return total / steps, total
 
 
 def rotating_sets(make, n_sets):
@@ -92,13 +170,9 @@ def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30):
     """Fused range compression in `mode`, rotating buffers totalling >= min_bytes."""
     import torch
     from paper_2605_28451_amd import api, scenes
-    sc = scenes.range_scene(seed=2, n_pulses=64, n=n)
+    sc = scenes.range_scene(seed=2, n_pulses=rows, n=n)
     fmt = api.storage_format(mode)
-    # replicate the 64 drawn pulses to `rows` (the kernel cost does not depend
-    # on the values; parity is checked on the drawn pulses)
-    base = api.to_device(sc.echo, fmt)
-    reps = (rows + 63) // 64
-    echo0 = base.repeat(reps, 1, 1)[:rows].contiguous()
+    echo0 = api.to_device(sc.echo, fmt)
     set_bytes = 2 * echo0.numel() * echo0.element_size()
     n_sets = max(1, -(-min_bytes // set_bytes))
     ins = [echo0 if i == 0 else echo0.clone() for i in range(n_sets)]
@@ -109,11 +183,11 @@ def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30):
     def launch(i):
         plan.range_compress(ins[i], H, out=outs[i])
 
-    per, total = time_launches(launch, n_sets, steps, warmup)
+    ms, total = time_launches(launch, n_sets, steps, warmup)
     res = {
         "mode": mode, "rows": rows, "n": n, "buffer_sets": n_sets,
         "working_set_mib": round(n_sets * set_bytes / 2 ** 20, 1),
-        "ms_per_launch": sum(per) / len(per),
+        "ms_per_launch": ms,
         "ms_total": total,
         "bytes_per_launch": set_bytes,
     }
@@ -122,9 +196,9 @@ def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30):
     # parity sample: first 64 pulses of the first output
     torch.cuda.synchronize()
     res["_sample_out"] = api.to_host(outs[0][:64], fmt)
-    res["_sample_in"] = scenes.quantize(sc.echo, fmt)
+    res["_sample_in"] = scenes.quantize(sc.echo[:64], fmt)
     res["_replica"] = sc.replica
-    del ins, outs, echo0, base
+    del ins, outs, echo0
     plan.close()
     torch.cuda.empty_cache()
     return res
@@ -141,8 +215,7 @@ def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30):
     ins = [x0 if i == 0 else x0.clone() for i in range(n_sets)]
     outs = [torch.empty_like(x0) for _ in range(n_sets)]
     plan = api.FFTPlan(n, rows, mode)
-    per, total = time_launches(lambda i: plan.forward(ins[i], out=outs[i]), n_sets, steps, warmup)
-    ms = sum(per) / len(per)
+    ms, total = time_launches(lambda i: plan.forward(ins[i], out=outs[i]), n_sets, steps, warmup)
     res = {"mode": mode, "rows": rows, "n": n, "buffer_sets": n_sets, "ms_per_launch": ms,
            "gflops": fft_flops(n, rows) / (ms * 1e-3) / 1e9,
            "hbm_gbs": set_bytes / (ms * 1e-3) / 1e9}
@@ -201,8 +274,7 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / (reps * n_frames)
     else:
-        per, total = time_launches(frame, n_frames, reps * n_frames, 0)
-        ms = total / (reps * n_frames)
+        ms, total = time_launches(frame, n_frames, reps * n_frames, 0)
     bytes_frame = 6 * echo0.numel() * echo0.element_size()  # RC r/w, CT r/w, AC r/w
     res = {"mode": mode, "ms_per_frame": ms, "frames_per_s": 1e3 / ms,
            "hbm_gbs": bytes_frame / (ms * 1e-3) / 1e9, "bytes_per_frame": bytes_frame,
@@ -226,8 +298,7 @@ def bench_uneven(mode, steps, warmup):
     ins = [x0, x0.clone()]
     outs = [torch.empty_like(x0) for _ in range(sets)]
     plan = api.UnevenPlan(ub.log2n, ub.inverse, mode)
-    per, total = time_launches(lambda i: plan.execute(ins[i], out=outs[i]), sets, steps, warmup)
-    ms = total / steps
+    ms, total = time_launches(lambda i: plan.execute(ins[i], out=outs[i]), sets, steps, warmup)
     sizes = (1 << ub.log2n.astype("int64"))
     import numpy as np
     flops = float(np.sum(5.0 * sizes * ub.log2n))
@@ -320,7 +391,18 @@ def main():
                     help="profiling mode: run only the fused range-compression kernel of the "
                          "given precision (e.g. fp16) for --steps launches, then a plain device "
                          "copy of the same bytes (counter calibration); prints no JSON")
+    ap.add_argument("--traffic-summary", nargs="+", metavar="MODE:FETCH_DIR:WRITE_DIR", default=None,
+                    help="write the HBM traffic record from rocprofv3 --pmc runs of --kernel-only "
+                         "(no GPU needed) and print its table")
+    ap.add_argument("--trace-summary", metavar="DIR", default=None,
+                    help="print the kernel table of a rocprofv3 --kernel-trace --stats run (no GPU needed)")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
+    if args.traffic_summary:
+        traffic_summary([tuple(a.split(":")) for a in args.traffic_summary])
+        return
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
               "(batches and SAR frames shard by row/frame with no exchange; see the design notes)",
@@ -340,8 +422,7 @@ def main():
               file=sys.stderr, flush=True)
         buf_in = torch.empty(r["bytes_per_launch"] // 2, dtype=torch.uint8, device="cuda")
         buf_out = torch.empty_like(buf_in)
-        per, _ = time_launches(lambda i: api.device_copy(buf_in, buf_out), 1, args.steps, args.warmup)
-        ms = sum(per) / len(per)
+        ms, _ = time_launches(lambda i: api.device_copy(buf_in, buf_out), 1, args.steps, args.warmup)
         print(f"[kernel-only] device copy of {buf_in.numel()} B: {ms:.4f} ms, "
               f"{2 * buf_in.numel() / (ms * 1e-3) / 1e9:.0f} GB/s (read + write)",
               file=sys.stderr, flush=True)

@@ -135,7 +135,9 @@ int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *fi
                            unsigned flags, void *stream);
 
 /* Tuning knobs of a plan.  engine: 0 = matrix cores where the mode and size
- * have them (BFP_FP16_MUL_FP32_ACC at n = 4096), 1 = vector ALU only.
+ * have them (BFP_FP16_MUL_FP32_ACC at n = 4096), 1 = vector ALU only (the
+ * default of a new plan: the faster engine on MI355X at every measured
+ * size; fft_autotune may still select 0).
  * blocks_per_cu: rows plans: 0 = one workgroup per group of rows, k > 0 = a
  * persistent grid of k workgroups per CU looping over the rows; uneven plans:
  * workgroups per CU of the persistent launch (0 or above the resident

@@ -182,7 +182,7 @@ class FFTPlan:
 
 
     # ------------------------------------------------------------ tuning
-    def set_tuning(self, engine: int = 0, blocks_per_cu: int = 0):
+    def set_tuning(self, engine: int = 1, blocks_per_cu: int = 0):
         check(_lib.load().fft_plan_set_tuning(self._h, int(engine), int(blocks_per_cu)),
               "fft_plan_set_tuning")
 
@@ -253,7 +253,7 @@ class UnevenPlan:
                 ctypes.POINTER(ctypes.c_longlong))), "fft_uneven_offsets")
 
     # ------------------------------------------------------------ tuning
-    def set_tuning(self, engine: int = 0, blocks_per_cu: int = 0):
+    def set_tuning(self, engine: int = 1, blocks_per_cu: int = 0):
         check(_lib.load().fft_plan_set_tuning(self._h, int(engine), int(blocks_per_cu)),
               "fft_plan_set_tuning")
 

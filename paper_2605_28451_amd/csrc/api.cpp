@@ -494,7 +494,7 @@ int fft_autotune(bfp_plan p, int op, const void *in, void *out, const void *filt
   } else {
     const bool mf = bfp::has_mfma_engine(p->prec, p->log2n);
     for (int e = 0; e <= (mf ? 1 : 0); ++e)
-      for (int b : {0, 1, 2, 4, 8}) cands.push_back({mf ? e : 1, b});
+      for (int b : {0, 1, 2, 3, 4, 5, 6, 8}) cands.push_back({mf ? e : 1, b});
   }
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;

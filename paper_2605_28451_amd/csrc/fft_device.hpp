@@ -52,8 +52,8 @@ __device__ __forceinline__ h2 csub(h2 a, h2 b) { return a - b; }
 __device__ __forceinline__ h2 csub_i(h2 a, h2 b) { return a + h2{b.y, -b.x}; }
 __device__ __forceinline__ h2 cadd_i(h2 a, h2 b) { return a + h2{-b.y, b.x}; }
 __device__ __forceinline__ h2 cmul(h2 a, h2 b) {
-  h2 t = h2{a.x, a.x} * b;                 // (ax bx, ax by)
-  return h2{a.y, a.y} * h2{-b.y, b.x} + t; // + (-ay by, ay bx)
+  const h2 t = b * h2{a.x, a.x};                                // (ax bx, ax by)
+  return __builtin_elementwise_fma(h2{-a.y, a.y}, b.yx, t);     // + (-ay by, ay bx)
 }
 __device__ __forceinline__ h2 cscale(h2 a, float s) { return a * h2{(f16)s, (f16)s}; }
 __device__ __forceinline__ h2 cconj(h2 a) { return h2{a.x, -a.y}; }
@@ -80,10 +80,18 @@ __device__ __forceinline__ c32 pow2(c32 a) {
   if constexpr (K == 0) return a;
   else return c32{__builtin_ldexpf(a.x, -K), __builtin_ldexpf(a.y, -K)};
 }
+// Packed FP16 variant: one v_pk_mul_f16 by (2^-K, +/-2^-K), the same
+// correctly rounded product as ldexp.  Contraction is off for this product,
+// so the compiler cannot fuse it into a neighbouring FMA.
+__device__ __forceinline__ h2 pk_scale(h2 a, h2 s) {
+#pragma clang fp contract(off)
+  return a * s;
+}
 template <int K>
 __device__ __forceinline__ h2 pow2(h2 a) {
+  static_assert(K >= 0 && K <= 14, "2^-K must be a normal FP16 number");
   if constexpr (K == 0) return a;
-  else return h2{ldexp16(a.x, -K), ldexp16(a.y, -K)};
+  else return pk_scale(a, h2{(f16)(1.0f / (1 << K)), (f16)(1.0f / (1 << K))});
 }
 // conj(a) . 2^-K
 template <int K>
@@ -93,8 +101,9 @@ __device__ __forceinline__ c32 conj_pow2(c32 a) {
 }
 template <int K>
 __device__ __forceinline__ h2 conj_pow2(h2 a) {
+  static_assert(K >= 0 && K <= 14, "2^-K must be a normal FP16 number");
   if constexpr (K == 0) return h2{a.x, -a.y};
-  else return h2{ldexp16(a.x, -K), (f16)-ldexp16(a.y, -K)};
+  else return pk_scale(a, h2{(f16)(1.0f / (1 << K)), (f16)(-1.0f / (1 << K))});
 }
 __device__ __forceinline__ c32 conj_store(c32 a) { return c32{a.x, -a.y}; }
 __device__ __forceinline__ h2 conj_store(h2 a) {
@@ -267,6 +276,31 @@ __device__ __forceinline__ uint32_t fp8_encode(float x) {
   return s | (r > rmax ? rmax : r);
 }
 
+// ------------------------------------------------------ streaming I/O ---
+// Row data is read once and written once: nontemporal loads and stores keep
+// it from displacing the twiddle and filter tables in the caches.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+  static_assert(sizeof(T) == 2 || sizeof(T) == 4 || sizeof(T) == 8, "unsupported element size");
+  if constexpr (sizeof(T) == 2)
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p)));
+  else if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(p)));
+  else
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p)));
+}
+template <class T>
+__device__ __forceinline__ void st_stream(T *p, T v) {
+  static_assert(sizeof(T) == 2 || sizeof(T) == 4 || sizeof(T) == 8, "unsupported element size");
+  if constexpr (sizeof(T) == 2)
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<uint16_t *>(p));
+  else if constexpr (sizeof(T) == 4)
+    __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, v), reinterpret_cast<uint32_t *>(p));
+  else
+    __builtin_nontemporal_store(__builtin_bit_cast(u32x2, v), reinterpret_cast<u32x2 *>(p));
+}
+
 // --------------------------------------------------- precision policies --
 // Each mode defines:
 //   Store: HBM element; Lds: on-chip element between passes;
@@ -276,8 +310,9 @@ __device__ __forceinline__ uint32_t fp8_encode(float x) {
 
 struct ModeFP32 {
   typedef c32 Store; typedef c32 Lds; typedef c32 Comp; typedef c32 Tw; typedef c32 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return p[i]; }
-  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { p[i] = v; }
+  static __device__ __forceinline__ Comp decode(Store s) { return s; }
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return ld_stream(p + i); }
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, v); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(v, w); }
@@ -287,8 +322,9 @@ struct ModeFP32 {
 
 struct ModeFP16 {  // pure packed FP16
   typedef h2 Store; typedef h2 Lds; typedef h2 Comp; typedef h2 Tw; typedef h2 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return p[i]; }
-  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { p[i] = v; }
+  static __device__ __forceinline__ Comp decode(Store s) { return s; }
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return ld_stream(p + i); }
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, v); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(v, w); }
@@ -301,8 +337,9 @@ __device__ __forceinline__ h2 c32_to_h2(c32 v) { return h2{(f16)v.x, (f16)v.y}; 
 
 struct ModeF16StoreF32 {
   typedef h2 Store; typedef h2 Lds; typedef c32 Comp; typedef c32 Tw; typedef h2 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return h2_to_c32(p[i]); }
-  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { p[i] = c32_to_h2(v); }
+  static __device__ __forceinline__ Comp decode(Store s) { return h2_to_c32(s); }
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return h2_to_c32(ld_stream(p + i)); }
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, c32_to_h2(v)); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return c32_to_h2(v); }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return h2_to_c32(v); }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(h2_to_c32(v), w); }
@@ -320,8 +357,9 @@ __device__ __forceinline__ c32 cmul_dot2(h2 a, h2 b) {
 
 struct ModeF16MulF32Acc {
   typedef h2 Store; typedef h2 Lds; typedef c32 Comp; typedef h2 Tw; typedef h2 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return h2_to_c32(p[i]); }
-  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { p[i] = c32_to_h2(v); }
+  static __device__ __forceinline__ Comp decode(Store s) { return h2_to_c32(s); }
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return h2_to_c32(ld_stream(p + i)); }
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, c32_to_h2(v)); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return c32_to_h2(v); }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return h2_to_c32(v); }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul_dot2(v, w); }
@@ -332,12 +370,12 @@ struct ModeF16MulF32Acc {
 template <int MANT, int BIAS>
 struct ModeFP8 {
   typedef fp8x2 Store; typedef c32 Lds; typedef c32 Comp; typedef c32 Tw; typedef c32 Filt;
-  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) {
-    fp8x2 b = p[i];
+  static __device__ __forceinline__ Comp decode(Store b) {
     return c32{fp8_decode<MANT, BIAS>(b.x), fp8_decode<MANT, BIAS>(b.y)};
   }
+  static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return decode(ld_stream(p + i)); }
   static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) {
-    p[i] = fp8x2{(uint8_t)fp8_encode<MANT, BIAS>(v.x), (uint8_t)fp8_encode<MANT, BIAS>(v.y)};
+    st_stream(p + i, fp8x2{(uint8_t)fp8_encode<MANT, BIAS>(v.x), (uint8_t)fp8_encode<MANT, BIAS>(v.y)});
   }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }

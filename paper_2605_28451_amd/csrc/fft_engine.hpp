@@ -108,7 +108,7 @@ struct Engine {
   // consumed its own, so their latency overlaps the butterflies and the LDS
   // exchange.  On exit v[e] holds the outputs (last pass) or the outputs
   // have been written to LDS.
-  template <int PASS>
+  template <int PASS, bool PREFETCH = true>
   static __device__ __forceinline__ void pass(Comp (&v)[E], Lds *lds, const Tw *__restrict__ tw,
                                               int t, Tw (&w)[E]) {
     constexpr int R = G::radix(PASS);
@@ -126,7 +126,7 @@ struct Engine {
         for (int r = 1; r < R; ++r) v[b + B * r] = M::twiddle(raw[b + B * r], w[b * R + r]);
       }
     }
-    load_tw<PASS + 1>(tw, t, w);
+    if constexpr (PREFETCH) load_tw<PASS + 1>(tw, t, w);
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       Comp u[R];
@@ -161,6 +161,28 @@ struct Engine {
     if constexpr (G::S::P > 1) pass<1>(v, lds, tw, t, w);
     if constexpr (G::S::P > 2) pass<2>(v, lds, tw, t, w);
     if constexpr (G::S::P > 3) pass<3>(v, lds, tw, t, w);
+  }
+
+  // ---- twiddles held in registers for a whole persistent kernel ----
+  // The rows of every pass (E values each), loaded once; a row then issues
+  // no global loads but its own data, so a load of the next row can stay in
+  // flight across the whole transform without any wait on the
+  // vector-memory counter catching it.  Used where the rows fit the
+  // register budget next to the data: packed FP16 data and twiddles and at
+  // most 3 passes.
+  static constexpr bool kTwRegs = sizeof(Tw) == 4 && sizeof(Comp) == 4 && G::S::P <= 3;
+  struct TwRegs {
+    Tw w[G::S::P > 1 ? G::S::P - 1 : 1][E];
+  };
+  static __device__ __forceinline__ void load_tw_regs(const Tw *__restrict__ tw, int t, TwRegs &W) {
+    if constexpr (G::S::P > 1) load_tw<1>(tw, t, W.w[0]);
+    if constexpr (G::S::P > 2) load_tw<2>(tw, t, W.w[1]);
+  }
+  static __device__ __forceinline__ void run_regs(Comp (&v)[E], Lds *lds, int t, TwRegs &W) {
+    static_assert(kTwRegs, "register twiddles need packed FP16 data and twiddles and at most 3 passes");
+    pass<0, false>(v, lds, nullptr, t, W.w[0]);
+    if constexpr (G::S::P > 1) pass<1, false>(v, lds, nullptr, t, W.w[0]);
+    if constexpr (G::S::P > 2) pass<2, false>(v, lds, nullptr, t, W.w[1]);
   }
 };
 

@@ -23,10 +23,25 @@
 //   p -> p ^ b67 ^ (b67 << 4) ^ (b1011 << 4),  b67 = p[7:6], b1011 = p[11:10],
 // which is conflict-free on 64 banks for every access below (checked by
 // simulation); each access resolves to four per-lane base registers plus
-// compile-time offsets.
+// compile-time offsets.  Two LDS buffers alternate between the exchanges, so
+// one barrier per exchange orders every write after the reads of the
+// buffer's previous contents.
 //
-// The operand slices and the dot-product-form twiddles come from a host
-// table built in FP64 and rounded once (see mfma4096_table).
+// Twiddles W_{16 NS}^{(j mod NS) r} are applied to the FP16 inputs of the
+// passes of span 16 and 256 as two v_dot2_f32_f16 per element (FP16 products,
+// FP32 sum) and rounded once to FP16.  The span-16 rows depend only on
+// (c, g), so each lane keeps its four for the whole kernel; the span-256
+// rows are fetched one pass ahead.
+//
+// Block-floating-point shift of the inverse (Eq. (1)): the first pass of a
+// BFP inverse uses S = F16 . 2^-12 instead of F16.  Every entry of F16 is 0
+// or has magnitude >= sin(pi/8), so S is exact in FP16, and because the FP16
+// x FP16 products are exact in FP32, the pass computes exactly
+// 2^-12 (F16 x) with FP32 accumulation: the shift costs no instruction and
+// no extra rounding.
+//
+// The operand slices and the twiddles come from a host table built in FP64
+// and rounded once (mfma4096_table).
 #pragma once
 
 #include "fft_device.hpp"
@@ -36,12 +51,26 @@ namespace bfp {
 typedef f16 half8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// Table layout in FP16 units (see mfma4096_table): F16 slices (64 lanes x
+// 16), S slices (64 x 16), span-16 twiddles (256 entries x 4), span-256
+// twiddles (4096 entries x 4); a twiddle entry is the pair of dot-product
+// operands (Re w, -Im w), (Im w, Re w).
+constexpr int kMfmaTwOffsetHalves = 2048;
+constexpr int kMfmaTw256OffsetHalves = kMfmaTwOffsetHalves + 4 * 256;
+
+// Twiddles of one pass for one lane: slot i of group m in t[2 m + i / 2]
+// (two entries per 16 bytes).
+struct MfmaTw {
+  uint4 t[8];
+};
+
 struct Mfma4096 {
   static constexpr int N = 4096;
-  static constexpr int TW_OFFSET_HALVES = 1024;  // twiddles follow the operand slices
 
-  half8 alo, ahi;              // DFT16 operand slices of this lane
-  const uint4 *tw;             // dot2-form twiddles, 8 bytes per entry
+  half8 alo, ahi;  // F16 operand slices of this lane
+  half8 slo, shi;  // F16 . 2^-12
+  uint4 tw16[2];   // span-16 twiddles of this lane (slots 0..3)
+  const uint4 *tw256;
   int w, c, g;
 
   __device__ __forceinline__ Mfma4096(const void *table, int tid) {
@@ -49,11 +78,18 @@ struct Mfma4096 {
     w = tid >> 6;
     c = lane & 15;
     g = lane >> 4;
-    const uint4 *a = reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(table) + 16 * lane);
-    const uint4 lo = a[0], hi = a[1];
-    alo = __builtin_bit_cast(half8, lo);
-    ahi = __builtin_bit_cast(half8, hi);
-    tw = reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(table) + TW_OFFSET_HALVES);
+    const uint16_t *tab = static_cast<const uint16_t *>(table);
+    const uint4 *a = reinterpret_cast<const uint4 *>(tab + 16 * lane);
+    const uint4 *s = reinterpret_cast<const uint4 *>(tab + 1024 + 16 * lane);
+    alo = __builtin_bit_cast(half8, a[0]);
+    ahi = __builtin_bit_cast(half8, a[1]);
+    slo = __builtin_bit_cast(half8, s[0]);
+    shi = __builtin_bit_cast(half8, s[1]);
+    // span 16: row j mod 16 = c for every group, entries r = 4g..4g+3
+    const uint4 *t16 = reinterpret_cast<const uint4 *>(tab + kMfmaTwOffsetHalves) + (c * 16 + 4 * g) / 2;
+    tw16[0] = t16[0];
+    tw16[1] = t16[1];
+    tw256 = reinterpret_cast<const uint4 *>(tab + kMfmaTw256OffsetHalves);
   }
 
   // element position of slot (m, i)
@@ -61,8 +97,21 @@ struct Mfma4096 {
     return (unsigned)(64 * w + 16 * m + c + 256 * (4 * g + i));
   }
 
-  // 64 butterflies: x[4m + i] (FP16) -> y[4m + i] (FP32)
+  // Twiddles of the pass of span 256: row j = 64 w + 16 m + c, entries r = 4g..4g+3.
+  __device__ __forceinline__ void load_tw256(MfmaTw &t) const {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const uint4 *p = tw256 + ((64 * w + 16 * m + c) * 16 + 4 * g) / 2;
+      t.t[2 * m] = p[0];
+      t.t[2 * m + 1] = p[1];
+    }
+  }
+
+  // 64 butterflies: x[4m + i] (FP16) -> y[4m + i] (FP32); SCALED selects S.
+  template <bool SCALED>
   __device__ __forceinline__ void dft(const h2 (&x)[16], c32 (&y)[16]) const {
+    const half8 lo = SCALED ? slo : alo;
+    const half8 hi = SCALED ? shi : ahi;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       half8 b;
@@ -72,8 +121,8 @@ struct Mfma4096 {
         b[2 * i + 1] = x[4 * m + i].y;
       }
       const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-      const f4 dlo = __builtin_amdgcn_mfma_f32_16x16x32_f16(alo, b, z, 0, 0, 0);
-      const f4 dhi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi, b, z, 0, 0, 0);
+      const f4 dlo = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo, b, z, 0, 0, 0);
+      const f4 dhi = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, b, z, 0, 0, 0);
       y[4 * m + 0] = c32{dlo[0], dlo[1]};
       y[4 * m + 1] = c32{dlo[2], dlo[3]};
       y[4 * m + 2] = c32{dhi[0], dhi[1]};
@@ -105,45 +154,59 @@ struct Mfma4096 {
     }
   }
 
-  // Inputs of the pass of span NS (16 or 256) from LDS, times the twiddles
-  // W_{16 NS}^{(j mod NS) r} with FP16 operands and FP32 accumulation.
-  template <int NS, int TW_ROW0>
-  __device__ __forceinline__ void gather(h2 (&x)[16], const h2 *lds) const {
+  // v . w as FP16 products with an FP32 sum, rounded once to FP16; tw holds
+  // the two dot-product forms of w.
+  static __device__ __forceinline__ h2 twiddle(h2 v, uint2 tw) {
+    const h2 w0 = __builtin_bit_cast(h2, tw.x), w1 = __builtin_bit_cast(h2, tw.y);
+    return c32_to_h2(c32{__builtin_amdgcn_fdot2(v, w0, 0.0f, false),
+                         __builtin_amdgcn_fdot2(v, w1, 0.0f, false)});
+  }
+
+  // Inputs of the pass of span 16 from LDS, times W_256^{(j mod 16) r}.
+  __device__ __forceinline__ void gather16(h2 (&x)[16], const h2 *lds) const {
     const int s = w ^ g;
     const int base = 64 * w + 1024 * g + (c ^ w);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int j = 64 * w + 16 * m + c;
-      const uint4 *tp = tw + (TW_ROW0 + (j & (NS - 1)) * 16 + 4 * g) / 2;  // 2 entries per uint4
-      const uint4 t01 = tp[0], t23 = tp[1];
-      h2 wt[8];
-      __builtin_memcpy(&wt[0], &t01, 16);
-      __builtin_memcpy(&wt[4], &t23, 16);
       const h2 *p = lds + base + 16 * (m ^ s);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const h2 v = p[256 * i];
-        const float re = __builtin_amdgcn_fdot2(v, wt[2 * i], 0.0f, false);
-        const float im = __builtin_amdgcn_fdot2(v, wt[2 * i + 1], 0.0f, false);
-        x[4 * m + i] = h2{(f16)re, (f16)im};
+        const uint4 t = tw16[i >> 1];
+        x[4 * m + i] = twiddle(p[256 * i], (i & 1) ? uint2{t.z, t.w} : uint2{t.x, t.y});
+      }
+    }
+  }
+
+  // Inputs of the pass of span 256 from LDS, times W_4096^{j r}.
+  __device__ __forceinline__ void gather256(h2 (&x)[16], const h2 *lds, const MfmaTw &tw) const {
+    const int s = w ^ g;
+    const int base = 64 * w + 1024 * g + (c ^ w);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const h2 *p = lds + base + 16 * (m ^ s);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint4 t = tw.t[2 * m + (i >> 1)];
+        x[4 * m + i] = twiddle(p[256 * i], (i & 1) ? uint2{t.z, t.w} : uint2{t.x, t.y});
       }
     }
   }
 
   // The transform: x = inputs at pos(m, i) (FP16) -> y = outputs X[pos(m, i)]
-  // (FP32).  lds: 4096 FP16 pairs per workgroup.
-  __device__ __forceinline__ void run(h2 (&x)[16], c32 (&y)[16], h2 *lds) const {
-    dft(x, y);  // span 1: no twiddles
+  // (FP32), scaled by 2^-12 when SCALED.  lds0, lds1: 4096 FP16 pairs each.
+  template <bool SCALED>
+  __device__ __forceinline__ void run(h2 (&x)[16], c32 (&y)[16], h2 *lds0, h2 *lds1) const {
+    MfmaTw t;
+    load_tw256(t);  // in flight during the first two passes
+    dft<SCALED>(x, y);
+    scatter1(y, lds0);
     __syncthreads();
-    scatter1(y, lds);
+    gather16(x, lds0);
+    dft<false>(x, y);
+    scatter16(y, lds1);
     __syncthreads();
-    gather<16, 0>(x, lds);
-    dft(x, y);
-    __syncthreads();
-    scatter16(y, lds);
-    __syncthreads();
-    gather<256, 256>(x, lds);
-    dft(x, y);
+    gather256(x, lds1, t);
+    dft<false>(x, y);
   }
 };
 

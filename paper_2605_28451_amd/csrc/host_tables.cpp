@@ -169,28 +169,32 @@ namespace bfp {
 //  [0, 1024): per lane l = c + 16 g (64 lanes), 8 halves of A_lo then 8 of
 //             A_hi: A[2q+s][2r+u] of the DFT16 (q over {0,1,4,5,8,9,12,13}
 //             for A_lo, +2 for A_hi; r = 4g + k/2, u = k % 2);
+//  [1024, 2048): the same slices times 2^-12 (first pass of a BFP inverse);
 //  then the inter-pass twiddles of the passes of span 16 and 256, entry
 //  (m, r) = W_{16 NS}^{m r} stored as the two dot-product operands
 //  (Re w, -Im w) and (Im w, Re w).
 std::vector<uint16_t> mfma4096_table() {
   std::vector<uint16_t> t;
-  t.reserve(1024 + 4 * (256 + 4096));
-  for (int l = 0; l < 64; ++l) {
-    const int row = l & 15, g = l >> 4, idx = row >> 1, s = row & 1;
-    const int q_lo = ((idx >> 1) << 2) + (idx & 1);
-    for (int half = 0; half < 2; ++half) {
-      const int q = q_lo + 2 * half;
-      for (int k = 0; k < 8; ++k) {
-        const int r = 4 * g + (k >> 1), u = k & 1;
-        const std::complex<double> w = unit_root((long long)q * r, 16);  // cos - i sin
-        const double cs = w.real(), sn = -w.imag();
-        double v;
-        if (s == 0) v = (u == 0) ? cs : sn;
-        else v = (u == 0) ? -sn : cs;
-        t.push_back(f64_to_f16_bits(v));
+  t.reserve(2048 + 4 * (256 + 4096));
+  // scale 0: F16; scale 1: F16 . 2^-12 (every nonzero entry has magnitude
+  // >= sin(pi/8), so the scaled value stays a normal FP16 number)
+  for (int scale = 0; scale < 2; ++scale)
+    for (int l = 0; l < 64; ++l) {
+      const int row = l & 15, g = l >> 4, idx = row >> 1, s = row & 1;
+      const int q_lo = ((idx >> 1) << 2) + (idx & 1);
+      for (int half = 0; half < 2; ++half) {
+        const int q = q_lo + 2 * half;
+        for (int k = 0; k < 8; ++k) {
+          const int r = 4 * g + (k >> 1), u = k & 1;
+          const std::complex<double> w = unit_root((long long)q * r, 16);  // cos - i sin
+          const double cs = w.real(), sn = -w.imag();
+          double v;
+          if (s == 0) v = (u == 0) ? cs : sn;
+          else v = (u == 0) ? -sn : cs;
+          t.push_back(f64_to_f16_bits(scale ? ldexp(v, -12) : v));
+        }
       }
     }
-  }
   for (int ns : {16, 256}) {
     const long long stride = 4096 / (ns * 16);
     for (int m = 0; m < ns; ++m)

@@ -33,7 +33,7 @@ struct RowArgs {
 // whether (mode, size) has a matrix-core engine
 inline bool has_mfma_engine(int mode, int log2n) { return mode == 3 && log2n == 12; }
 // bytes of the matrix-core table (operand slices + dot2-form twiddles)
-constexpr int kMfmaTableBytes = 2 * (1024 + 4 * (256 + 4096));
+constexpr int kMfmaTableBytes = 2 * (2048 + 4 * (256 + 4096));
 
 // Launch a row kernel; returns hipSuccess or the launch error.
 hipError_t launch_rows(int mode, int log2n, int op, bool out32, const RowArgs &a,

@@ -28,7 +28,7 @@ struct bfp_plan_s {
   int *order_d = nullptr;
   int grid = 0;
   // tuning knobs (fft_plan_set_tuning / fft_autotune)
-  int tune_engine = 0;     // 0: matrix cores where available, 1: vector ALU only
+  int tune_engine = 1;     // 0: matrix cores where available, 1: vector ALU (default)
   int tune_bpc = 0;        // workgroups per CU of a persistent grid, 0 = default
   int cu_count = 0;
   int uneven_max_bpc = 1;

@@ -48,7 +48,11 @@ __device__ __forceinline__ h2 mul_c32(h2 v, c32 p) { return cmul(v, c32_to_h2(p)
 // conjugated filter (adjoint), per-pulse phasor at load.
 enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4 };
 
-template <class M, int LOG2N, int OP, int V, bool OUT32>
+// PIPE (persistent grids, where the engine keeps its twiddles in registers):
+// the twiddle rows are loaded once per workgroup, and the next row group's
+// data is loaded into registers while the current group is transformed, so
+// HBM reads overlap the arithmetic instead of alternating with it.
+template <class M, int LOG2N, int OP, int V, bool OUT32, bool PIPE>
 __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   typedef Geometry<LOG2N> G;
   typedef Engine<M, LOG2N> EN;
@@ -67,51 +71,95 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   const unsigned t = threadIdx.x & (T - 1);
   typename M::Lds *lds = lds_all + local * G::LDS_N;
   const Tw *tw = static_cast<const Tw *>(a.tw);
+  // A 4-byte filter (FP16 pairs) is the same for every row: its E values
+  // per thread are loaded once, ahead of the row loop, so no row waits on
+  // them.  Wider filters are read per row to keep registers free.
+  const Filt *f = static_cast<const Filt *>(a.filter);
+  constexpr bool kHoist = sizeof(Filt) == 4 && OP != OP_FWD;
+  Filt hf[kHoist ? E : 1];
+  if constexpr (kHoist) {
+    if (f) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) hf[e] = f[t + T * e];
+    }
+  }
   // workgroups loop over groups of TPW rows (one iteration unless the grid
   // was limited to a persistent size); every thread takes the same trips
   const int groups = (a.rows + G::TPW - 1) / G::TPW;
+  static_assert(!PIPE || EN::kTwRegs, "the pipelined kernel keeps its twiddles in registers");
+  typename EN::TwRegs W;
+  Store nx[PIPE ? E : 1];
+  if constexpr (PIPE) {
+    EN::load_tw_regs(tw, t, W);
+    const long long row0 = (long long)blockIdx.x * G::TPW + local;
+    if (row0 < a.rows) {
+      const Store *src = static_cast<const Store *>(a.in) + row0 * N + t;
+#pragma unroll
+      for (int e = 0; e < E; ++e) nx[e] = ld_stream(src + (unsigned)(T * e));
+    }
+  }
+  auto transform = [&](Comp (&x)[E]) {
+    if constexpr (PIPE) EN::run_regs(x, lds, t, W);
+    else EN::run(x, lds, tw, t);
+  };
   for (int grp = blockIdx.x; grp < groups; grp += gridDim.x) {
   const long long row = (long long)grp * G::TPW + local;
   const bool active = row < a.rows;
 
   Comp v[E];
   if (active) {
-    // one per-thread base, element offsets T e as immediates
-    const Store *src = static_cast<const Store *>(a.in) + row * N + t;
+    if constexpr (PIPE) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = M::load(src, (unsigned)(T * e));
+      for (int e = 0; e < E; ++e) v[e] = M::decode(nx[e]);
+    } else {
+      // one per-thread base, element offsets T e as immediates
+      const Store *src = static_cast<const Store *>(a.in) + row * N + t;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = M::load(src, (unsigned)(T * e));
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = Comp{};
   }
+  if constexpr (OP == OP_COMPRESS && phasor) {
+    if (active) {
+      const c32 *ph = static_cast<const c32 *>(a.phasor) + t;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = mul_c32(v[e], ph[T * e]);
+    }
+  }
+  if constexpr (PIPE) {
+    // the next group's data, in flight during this group's transforms
+    const long long nrow = row + (long long)gridDim.x * G::TPW;
+    if (grp + (int)gridDim.x < groups && nrow < a.rows) {
+      const Store *src = static_cast<const Store *>(a.in) + nrow * N + t;
+#pragma unroll
+      for (int e = 0; e < E; ++e) nx[e] = ld_stream(src + (unsigned)(T * e));
+    }
+  }
 
   if constexpr (OP == OP_FWD) {
-    EN::run(v, lds, tw, t);
+    transform(v);
   } else {
-    if constexpr (OP == OP_COMPRESS) {
-      if constexpr (phasor) {
-        const c32 *ph = static_cast<const c32 *>(a.phasor) + t;
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = mul_c32(v[e], ph[T * e]);
-      }
-      EN::run(v, lds, tw, t);
-    }
+    if constexpr (OP == OP_COMPRESS) transform(v);
     // BFP fold at the inverse's load: conj(z . H) . 2^-log2N, or with the
     // conjugated filter conj(z . conj H) = conj(z) . H
     constexpr int K = naive ? 0 : LOG2N;  // block shift 2^-log2N
-    const Filt *f = static_cast<const Filt *>(a.filter);
-    if (f) {
-      const Filt *ft = f + t;
+    // compression always carries a filter (checked by the C layer), so its
+    // kernels have no run-time branch here
+    if (OP == OP_COMPRESS || f) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const Filt h = ft[T * e];
+        Filt h;
+        if constexpr (kHoist) h = hf[e];
+        else h = f[t + T * e];
         v[e] = conj_f ? pow2<K>(M::fmul(cconj(v[e]), h)) : conj_pow2<K>(M::fmul(v[e], h));
       }
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = conj_pow2<K>(v[e]);
     }
-    EN::run(v, lds, tw, t);
+    transform(v);
     if constexpr (naive) {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = pow2<LOG2N>(M::round_store(cconj(v[e])));
@@ -125,7 +173,7 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
     if constexpr (OUT32) {
       c32 *dst = static_cast<c32 *>(a.out) + row * N + t;
 #pragma unroll
-      for (int e = 0; e < E; ++e) dst[(unsigned)(T * e)] = to_c32(v[e]);
+      for (int e = 0; e < E; ++e) st_stream(dst + (unsigned)(T * e), to_c32(v[e]));
     } else {
       Store *dst = static_cast<Store *>(a.out) + row * N + t;
 #pragma unroll
@@ -153,15 +201,29 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
 // Products with the filter take FP16 operands: X is rounded to FP16 as the
 // two dot-product forms (Re X, -Im X) and (Im X, Re X), so
 // Re(X H) = (Re X, -Im X) . H and Im(X H) = (Im X, Re X) . H accumulate in
-// FP32; conj(X) H uses (Re X, Im X) and (-Im X, Re X).
+// FP32; conj(X) H uses (Re X, Im X) and (-Im X, Re X).  The conjugated
+// product is rounded once to FP16, and the exact 2^-12 shift of Eq. (1) is
+// the scaled operand of the inverse's first pass.
 template <int OP, int V, bool OUT32>
 __global__ void __launch_bounds__(256) row_kernel_mfma(RowArgs a) {
   constexpr int N = 4096;
   constexpr bool naive = (V & V_NAIVE) != 0;
   constexpr bool conj_f = (V & V_CONJ) != 0;
   constexpr bool phasor = (V & V_PHASOR) != 0;
-  __shared__ h2 lds[N];
+  __shared__ h2 lds[2][N];
   const Mfma4096 E(a.tw, threadIdx.x);
+  // the filter is the same for every row: its 16 values per thread are
+  // loaded once, ahead of the row loop, so no row waits on them
+  const h2 *f = static_cast<const h2 *>(a.filter);
+  h2 hf[16];
+  if constexpr (OP != OP_FWD) {
+    if (f) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hf[4 * m + i] = f[E.pos(m, i)];
+    }
+  }
   for (long long row = blockIdx.x; row < a.rows; row += gridDim.x) {
   h2 x[16];
   c32 y[16];
@@ -169,7 +231,7 @@ __global__ void __launch_bounds__(256) row_kernel_mfma(RowArgs a) {
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x[4 * m + i] = src[E.pos(m, i)];
+    for (int i = 0; i < 4; ++i) x[4 * m + i] = ld_stream(src + E.pos(m, i));
 
   if constexpr (OP != OP_FWD) {
     if constexpr (OP == OP_COMPRESS) {
@@ -181,38 +243,33 @@ __global__ void __launch_bounds__(256) row_kernel_mfma(RowArgs a) {
           for (int i = 0; i < 4; ++i)
             x[4 * m + i] = c32_to_h2(cmul(h2_to_c32(x[4 * m + i]), ph[E.pos(m, i)]));
       }
-      E.run(x, y, lds);
+      E.run<false>(x, y, lds[0], lds[1]);
     } else {
 #pragma unroll
       for (int k = 0; k < 16; ++k) y[k] = h2_to_c32(x[k]);
     }
-    // BFP fold: conj(z . H) . 2^-12 (exact), FP16 operands, FP32 sums
-    constexpr int K = naive ? 0 : 12;  // block shift 2^-12
-    const h2 *f = static_cast<const h2 *>(a.filter);
+    // BFP fold: conj(z . H) (or conj(z) . H) here, 2^-12 in the next pass;
+    // compression always carries a filter (checked by the C layer)
+    if (OP == OP_COMPRESS || f) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = 4 * m + i;
-        c32 z;
-        if (f) {
-          const h2 h = f[E.pos(m, i)];
-          if constexpr (conj_f) {
-            const h2 xa = c32_to_h2(c32{y[k].x, y[k].y}), xb = c32_to_h2(c32{-y[k].y, y[k].x});
-            z = pow2<K>(c32{__builtin_amdgcn_fdot2(xa, h, 0.0f, false),
-                            __builtin_amdgcn_fdot2(xb, h, 0.0f, false)});
-          } else {
-            const h2 xa = c32_to_h2(c32{y[k].x, -y[k].y}), xb = c32_to_h2(c32{y[k].y, y[k].x});
-            z = conj_pow2<K>(c32{__builtin_amdgcn_fdot2(xa, h, 0.0f, false),
-                                 __builtin_amdgcn_fdot2(xb, h, 0.0f, false)});
-          }
+      for (int k = 0; k < 16; ++k) {
+        const h2 h = hf[k];
+        if constexpr (conj_f) {
+          const h2 xa = c32_to_h2(c32{y[k].x, y[k].y}), xb = c32_to_h2(c32{-y[k].y, y[k].x});
+          x[k] = c32_to_h2(c32{__builtin_amdgcn_fdot2(xa, h, 0.0f, false),
+                               __builtin_amdgcn_fdot2(xb, h, 0.0f, false)});
         } else {
-          z = conj_pow2<K>(y[k]);
+          const h2 xa = c32_to_h2(c32{y[k].x, -y[k].y}), xb = c32_to_h2(c32{y[k].y, y[k].x});
+          x[k] = c32_to_h2(c32{__builtin_amdgcn_fdot2(xa, h, 0.0f, false),
+                               -__builtin_amdgcn_fdot2(xb, h, 0.0f, false)});
         }
-        x[k] = c32_to_h2(z);
       }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = c32_to_h2(cconj(y[k]));
+    }
   }
-  E.run(x, y, lds);
+  E.run<OP != OP_FWD && !naive>(x, y, lds[0], lds[1]);
   if constexpr (OP != OP_FWD) {
 #pragma unroll
     for (int k = 0; k < 16; ++k)
@@ -224,13 +281,13 @@ __global__ void __launch_bounds__(256) row_kernel_mfma(RowArgs a) {
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dst[E.pos(m, i)] = y[4 * m + i];
+      for (int i = 0; i < 4; ++i) st_stream(dst + E.pos(m, i), y[4 * m + i]);
   } else {
     h2 *dst = static_cast<h2 *>(a.out) + row * N;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dst[E.pos(m, i)] = c32_to_h2(y[4 * m + i]);
+      for (int i = 0; i < 4; ++i) st_stream(dst + E.pos(m, i), c32_to_h2(y[4 * m + i]));
   }
   if (a.flags & KF_CHECK_FINITE) {
     unsigned bad = 0;
@@ -262,7 +319,13 @@ static hipError_t launch_one(const RowArgs &a, hipStream_t s) {
 #endif
   unsigned grid = (unsigned)((a.rows + G::TPW - 1) / G::TPW);
   if (a.grid_limit > 0 && grid > (unsigned)a.grid_limit) grid = (unsigned)a.grid_limit;
-  hipLaunchKernelGGL((row_kernel<MODE, LOG2N, OP, V, OUT32>), dim3(grid), dim3(G::WG), 0, s, a);
+  if constexpr (Engine<MODE, LOG2N>::kTwRegs) {
+    if (a.grid_limit > 0) {
+      hipLaunchKernelGGL((row_kernel<MODE, LOG2N, OP, V, OUT32, true>), dim3(grid), dim3(G::WG), 0, s, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((row_kernel<MODE, LOG2N, OP, V, OUT32, false>), dim3(grid), dim3(G::WG), 0, s, a);
   return hipGetLastError();
 }
 

@@ -132,22 +132,40 @@ hipError_t launch_phasor(const float *phase, void *phasor, int n, int negate, hi
 }
 
 // ------------------------------------------------------------- copy ------
-// Plain streaming copy, 16 bytes per lane per iteration: the reference for
-// achievable HBM bandwidth and for calibrating memory counters.
-__global__ void __launch_bounds__(256) copy_kernel(const uint4 *__restrict__ in,
-                                                   uint4 *__restrict__ out, long long n16) {
+// Plain streaming copy: the reference for achievable HBM bandwidth and for
+// calibrating memory counters.  Each thread keeps four 16-byte loads in
+// flight (the workgroup moves 16 KiB per trip, lanes contiguous within each
+// 4 KiB slice); the tail that is not a whole 16 KiB chunk is copied by a
+// second, element-wise loop.
+constexpr int kCopyUnroll = 4;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) copy_kernel(const u32x4 *__restrict__ in,
+                                                   u32x4 *__restrict__ out, long long n16) {
+  const long long chunk = 256LL * kCopyUnroll;
+  const long long chunks = n16 / chunk;
+  for (long long c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const u32x4 *src = in + c * chunk + threadIdx.x;
+    u32x4 *dst = out + c * chunk + threadIdx.x;
+    u32x4 v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(src + 256 * u);
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + 256 * u);
+  }
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+  for (long long i = chunks * chunk + (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += stride)
     out[i] = in[i];
 }
 
 hipError_t launch_copy(const void *in, void *out, long long bytes, hipStream_t s) {
   const long long n16 = bytes / 16;
   if (n16 <= 0) return hipSuccess;
-  long long blocks = (n16 + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  long long blocks = (n16 + 256LL * kCopyUnroll - 1) / (256LL * kCopyUnroll);
+  if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
-                     static_cast<const uint4 *>(in), static_cast<uint4 *>(out), n16);
+                     static_cast<const u32x4 *>(in), static_cast<u32x4 *>(out), n16);
   return hipGetLastError();
 }
 
