@@ -82,12 +82,17 @@ enum bfp_flags {
   /* Count non-finite output values into the plan's counter
    * (read with fft_plan_nonfinite). */
   BFP_FLAG_CHECK_FINITE = 2u,
+  /* sar_range_compress only: store the result corner-turned, rc_t[range]
+   * [pulse] (n x n_pulses), as sar_corner_turn would leave it (the corner
+   * turn fused into the compression's store). */
+  BFP_FLAG_TRANSPOSED_STORE = 4u,
   /* Output stored as interleaved FP32 whatever the precision mode. */
   BFP_FLAG_OUT_FP32 = 8u,
   /* Use conj(filter): the adjoint of the compression chain. */
   BFP_FLAG_CONJ_FILTER = 16u,
   /* Plan flag: allocate the autofocus workspace (FP32 twiddles and the
-   * phase-gradient partial sums, up to 16 MiB at n = 16384). */
+   * phase-gradient partial sums: 1024 workgroups x n floats per transform
+   * a workgroup holds, 16 MiB at n = 4096, 64 MiB at n = 16384). */
   BFP_FLAG_AUTOFOCUS = 32u
 };
 
@@ -138,8 +143,11 @@ int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *fi
  * have them (BFP_FP16_MUL_FP32_ACC at n = 4096), 1 = vector ALU only (the
  * default of a new plan: the faster engine on MI355X at every measured
  * size; fft_autotune may still select 0).
- * blocks_per_cu: rows plans: 0 = one workgroup per group of rows, k > 0 = a
- * persistent grid of k workgroups per CU looping over the rows; uneven plans:
+ * blocks_per_cu: rows plans: -1 = automatic (the default of a new plan:
+ * the fused compression of pure FP16 at n <= 4096 uses k = 3, everything
+ * else 0), 0 = one workgroup per group of rows, k > 0 = a persistent grid of
+ * k workgroups per CU looping over the rows (in pure FP16 at n <= 4096 this
+ * grid overlaps the next rows' loads with the current rows' transforms); uneven plans:
  * workgroups per CU of the persistent launch (0 or above the resident
  * maximum = the maximum).  Results do not depend on blocks_per_cu. */
 int fft_plan_set_tuning(bfp_plan p, int engine, int blocks_per_cu);
@@ -197,7 +205,9 @@ int bfp_device_copy(const void *in, void *out, long long bytes, void *stream);
  * write per row.  range_plan: n = range samples, its mode sets the storage
  * type; n_pulses <= plan batch is the number of rows processed.  h_range:
  * n elements in bfp_filter_format(prec).  flags: BFP_FLAG_NAIVE_POSTSCALE,
- * BFP_FLAG_CONJ_FILTER, BFP_FLAG_OUT_FP32, BFP_FLAG_CHECK_FINITE. */
+ * BFP_FLAG_CONJ_FILTER, BFP_FLAG_OUT_FP32, BFP_FLAG_CHECK_FINITE,
+ * BFP_FLAG_TRANSPOSED_STORE (rc is then n x n_pulses, range-major: the
+ * layout sar_azimuth_compress reads, with no separate corner turn). */
 int sar_range_compress(bfp_plan range_plan, const void *echo, void *rc, const void *h_range,
                        int n_pulses, unsigned flags, void *stream);
 

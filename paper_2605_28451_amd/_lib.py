@@ -29,6 +29,7 @@ FILTER_OF = {0: "fp32", 1: "fp16", 2: "fp16", 3: "fp16", 4: "fp32", 5: "fp32"}
 # bfp_flags
 FLAG_NAIVE_POSTSCALE = 1
 FLAG_CHECK_FINITE = 2
+FLAG_TRANSPOSED_STORE = 4
 FLAG_OUT_FP32 = 8
 FLAG_CONJ_FILTER = 16
 FLAG_AUTOFOCUS = 32

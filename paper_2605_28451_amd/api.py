@@ -12,7 +12,7 @@ import torch
 
 from . import _lib
 from ._lib import (FILTER_OF, FLAG_CHECK_FINITE, FLAG_CONJ_FILTER, FLAG_NAIVE_POSTSCALE,
-                   FLAG_OUT_FP32, FORMATS, PRECISIONS, STORAGE_OF, check)
+                   FLAG_OUT_FP32, FLAG_TRANSPOSED_STORE, FORMATS, PRECISIONS, STORAGE_OF, check)
 
 TORCH_DTYPE = {"fp32": torch.float32, "fp16": torch.float16, "e4m3": torch.uint8, "e5m2": torch.uint8}
 
@@ -157,11 +157,19 @@ class FFTPlan:
         return out
 
     def range_compress(self, echo, filt, out=None, rows=None, naive=False, out_fp32=False,
-                       stream=None):
+                       transposed=False, stream=None):
+        """transposed=True stores the result corner-turned, shape (n, rows):
+        the layout azimuth_compress reads (the corner turn fused into the store)."""
         rows = self._rows_of(echo, rows)
-        out = self._out(out, rows, out_fp32 or bool(self.flags & FLAG_OUT_FP32))
+        if transposed:
+            if out is None:
+                out = empty((self.n, rows), self.fmt)
+            _check_storage(out, self.fmt, rows * self.n, "output")
+        else:
+            out = self._out(out, rows, out_fp32 or bool(self.flags & FLAG_OUT_FP32))
         _check_storage(filt, self.filter_fmt, self.n, "filter")
-        fl = (FLAG_NAIVE_POSTSCALE if naive else 0) | (FLAG_OUT_FP32 if out_fp32 else 0)
+        fl = ((FLAG_NAIVE_POSTSCALE if naive else 0) | (FLAG_OUT_FP32 if out_fp32 else 0) |
+              (FLAG_TRANSPOSED_STORE if transposed else 0))
         check(_lib.load().sar_range_compress(self._h, _ptr(echo), _ptr(out), _ptr(filt), rows, fl,
                                              _stream(stream)), "sar_range_compress")
         return out
@@ -182,7 +190,7 @@ class FFTPlan:
 
 
     # ------------------------------------------------------------ tuning
-    def set_tuning(self, engine: int = 1, blocks_per_cu: int = 0):
+    def set_tuning(self, engine: int = 1, blocks_per_cu: int = -1):
         check(_lib.load().fft_plan_set_tuning(self._h, int(engine), int(blocks_per_cu)),
               "fft_plan_set_tuning")
 

@@ -21,6 +21,20 @@ using bfp::RowArgs;
 
 namespace {
 
+// blocks_per_cu = kAutoBpc: the fused compression of pure FP16 up to n = 4096
+// runs the pipelined persistent kernel with 3 workgroups per CU (its
+// register budget allows 3 resident per CU; measured best at 2048 and 16384
+// rows of 4096); every other operation one workgroup per row group (the
+// single transforms are faster at full occupancy).
+constexpr int kAutoBpc = -1;
+constexpr int kPipelinedBpc = 3;
+
+int effective_bpc(const bfp_plan_s *p, int op) {
+  if (p->tune_bpc != kAutoBpc) return p->tune_bpc;
+  return (op == bfp::OP_COMPRESS && p->prec == BFP_FP16 && p->log2n <= 12) ? kPipelinedBpc : 0;
+}
+
+
 thread_local std::string g_last_error;
 
 int fail(int status, const std::string &msg) {
@@ -138,6 +152,7 @@ unsigned kflags(unsigned f) {
   if (f & BFP_FLAG_NAIVE_POSTSCALE) k |= bfp::KF_NAIVE;
   if (f & BFP_FLAG_CHECK_FINITE) k |= bfp::KF_CHECK_FINITE;
   if (f & BFP_FLAG_CONJ_FILTER) k |= bfp::KF_CONJ_FILTER;
+  if (f & BFP_FLAG_TRANSPOSED_STORE) k |= bfp::KF_TRANSPOSED;
   return k;
 }
 
@@ -157,7 +172,8 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   a.phasor = phasor;
   a.flags = kflags(flags | p->flags);
   a.nonfinite = p->nonfinite;
-  a.grid_limit = p->tune_bpc > 0 ? p->tune_bpc * p->cu_count : 0;
+  const int bpc = effective_bpc(p, op);
+  a.grid_limit = bpc > 0 ? bpc * p->cu_count : 0;
   a.engine = p->tune_engine;
   const bool out32 = ((flags | p->flags) & BFP_FLAG_OUT_FP32) != 0;
   int cur = 0;
@@ -255,6 +271,9 @@ int fft_plan(bfp_plan *out, int n, int batch, int prec, unsigned flags) {
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) p->cu_count = prop.multiProcessorCount;
     if (p->cu_count <= 0) p->cu_count = 1;
   }
+  // default tuning: the vector engine, grid chosen per operation
+  p->tune_engine = 1;
+  p->tune_bpc = kAutoBpc;
   st = upload_twiddles(l, prec, &p->tw);
   if (st) {
     free_plan(p);
@@ -364,8 +383,12 @@ int sar_range_compress(bfp_plan range_plan, const void *echo, void *rc, const vo
   if (st) return st;
   if (!h_range) return fail(BFP_EINVAL, "range filter is NULL");
   if (flags & ~(unsigned)(BFP_FLAG_NAIVE_POSTSCALE | BFP_FLAG_CHECK_FINITE | BFP_FLAG_CONJ_FILTER |
-                          BFP_FLAG_OUT_FP32))
+                          BFP_FLAG_OUT_FP32 | BFP_FLAG_TRANSPOSED_STORE))
     return fail(BFP_EINVAL, "unknown flag for sar_range_compress");
+  if ((flags & BFP_FLAG_TRANSPOSED_STORE) &&
+      ((flags | range_plan->flags) &
+       (BFP_FLAG_NAIVE_POSTSCALE | BFP_FLAG_CONJ_FILTER | BFP_FLAG_OUT_FP32)))
+    return fail(BFP_EUNSUPPORTED, "BFP_FLAG_TRANSPOSED_STORE combines with BFP_FLAG_CHECK_FINITE only");
   if (echo == rc) return fail(BFP_EINVAL, "echo and rc must differ");
   return run_rows(range_plan, bfp::OP_COMPRESS, echo, rc, h_range, nullptr, n_pulses, flags,
                   stream);
@@ -465,7 +488,9 @@ int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, co
 int fft_plan_set_tuning(bfp_plan p, int engine, int blocks_per_cu) {
   if (!p) return fail(BFP_EINVAL, "plan is NULL");
   if (engine < 0 || engine > 1) return fail(BFP_EINVAL, "engine must be 0 or 1");
-  if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(BFP_EINVAL, "blocks_per_cu must be in [0, 64]");
+  if (blocks_per_cu < -1 || blocks_per_cu > 64)
+    return fail(BFP_EINVAL, "blocks_per_cu must be -1 (automatic) or in [0, 64]");
+  if (p->kind == 1 && blocks_per_cu < 0) return fail(BFP_EINVAL, "uneven plans take blocks_per_cu >= 0");
   if (p->kind == 1) {
     const int b = blocks_per_cu == 0 ? p->uneven_max_bpc : std::min(blocks_per_cu, p->uneven_max_bpc);
     p->grid = b * p->cu_count;
@@ -494,7 +519,7 @@ int fft_autotune(bfp_plan p, int op, const void *in, void *out, const void *filt
   } else {
     const bool mf = bfp::has_mfma_engine(p->prec, p->log2n);
     for (int e = 0; e <= (mf ? 1 : 0); ++e)
-      for (int b : {0, 1, 2, 3, 4, 5, 6, 8}) cands.push_back({mf ? e : 1, b});
+      for (int b : {kAutoBpc, 0, 1, 2, 3, 4, 5, 6, 8}) cands.push_back({mf ? e : 1, b});
   }
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;

@@ -32,9 +32,10 @@ __global__ void __launch_bounds__(256) entropy_partial_kernel(const c32 *__restr
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
     const c32 v = img[i];
-    const double a = (double)v.x * v.x + (double)v.y * v.y;
+    // |I|^2 and its logarithm in FP32 (the image is FP32), sums in FP64
+    const float a = v.x * v.x + v.y * v.y;
     s += a;
-    if (a > 0.0) q += a * log(a);
+    if (a > 0.0f) q += (double)a * (double)logf(a);
   }
   sh[0][threadIdx.x] = s;
   sh[1][threadIdx.x] = q;
@@ -183,13 +184,28 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
   for (int e = 0; e < E; ++e) dst[t + T * e] = acc[e];
 }
 
+// out[m] = sum over p of partial[p][m] in a fixed order, in two steps:
+// partial_sum_kernel adds part chunk c (parts [c P/C, (c+1) P/C)) of 64
+// columns per workgroup, 4 interleaved slices per column combined in slice
+// order, into stage[c][m]; the same kernel over the C stage rows (one chunk)
+// gives out[m].
+constexpr int kSumChunks = 16;
+
 __global__ void __launch_bounds__(256) partial_sum_kernel(const float *__restrict__ partial, int parts,
                                                           int n, float *__restrict__ out) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
+  __shared__ double sh[4][64];
+  const int c = threadIdx.x & 63, slice = threadIdx.x >> 6;
+  const int m = blockIdx.x * 64 + c;
+  const int chunks = gridDim.y;
+  const int p0 = (int)(((long long)parts * blockIdx.y) / chunks);
+  const int p1 = (int)(((long long)parts * (blockIdx.y + 1)) / chunks);
   double s = 0.0;
-  for (int p = 0; p < parts; ++p) s += partial[(long long)p * n + m];
-  out[m] = (float)s;
+  if (m < n)
+    for (int p = p0 + slice; p < p1; p += 4) s += partial[(long long)p * n + m];
+  sh[slice][c] = s;
+  __syncthreads();
+  if (slice == 0 && m < n)
+    out[(long long)blockIdx.y * n + m] = (float)(((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c]);
 }
 
 template <class StoreT, int LOG2N>
@@ -202,8 +218,14 @@ static hipError_t launch_pg(const PhaseGradArgs &a, bool fused, int grid, hipStr
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = G::N;
-  hipLaunchKernelGGL(partial_sum_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a.partial,
-                     grid * G::TPW, n, a.grad);
+  const int parts = grid * G::TPW;
+  float *stage = a.partial + (long long)kPhaseGradBlocks * G::TPW * n;  // kSumChunks rows
+  hipLaunchKernelGGL(partial_sum_kernel, dim3((n + 63) / 64, kSumChunks), dim3(256), 0, s, a.partial,
+                     parts, n, stage);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(partial_sum_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, s, stage, kSumChunks,
+                     n, a.grad);
   return hipGetLastError();
 }
 
@@ -218,7 +240,8 @@ int phase_grad_grid(int log2n, int rows) {
 long long phase_grad_scratch_floats(int log2n) {
   const int T = threads_per_transform(log2n);
   const int wg = T < 256 ? 256 : T;
-  return (long long)kPhaseGradBlocks * (wg / T) * (1ll << log2n);
+  // per-workgroup partial rows, then the kSumChunks rows of the first sum
+  return ((long long)kPhaseGradBlocks * (wg / T) + kSumChunks) * (1ll << log2n);
 }
 
 hipError_t launch_phase_grad(bool fp16_storage, int log2n, const PhaseGradArgs &a, bool fused,

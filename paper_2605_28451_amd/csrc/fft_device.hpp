@@ -311,6 +311,7 @@ __device__ __forceinline__ void st_stream(T *p, T v) {
 struct ModeFP32 {
   typedef c32 Store; typedef c32 Lds; typedef c32 Comp; typedef c32 Tw; typedef c32 Filt;
   static __device__ __forceinline__ Comp decode(Store s) { return s; }
+  static __device__ __forceinline__ Store encode(Comp v) { return v; }
   static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return ld_stream(p + i); }
   static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, v); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
@@ -323,6 +324,7 @@ struct ModeFP32 {
 struct ModeFP16 {  // pure packed FP16
   typedef h2 Store; typedef h2 Lds; typedef h2 Comp; typedef h2 Tw; typedef h2 Filt;
   static __device__ __forceinline__ Comp decode(Store s) { return s; }
+  static __device__ __forceinline__ Store encode(Comp v) { return v; }
   static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return ld_stream(p + i); }
   static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, v); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
@@ -338,6 +340,7 @@ __device__ __forceinline__ h2 c32_to_h2(c32 v) { return h2{(f16)v.x, (f16)v.y}; 
 struct ModeF16StoreF32 {
   typedef h2 Store; typedef h2 Lds; typedef c32 Comp; typedef c32 Tw; typedef h2 Filt;
   static __device__ __forceinline__ Comp decode(Store s) { return h2_to_c32(s); }
+  static __device__ __forceinline__ Store encode(Comp v) { return c32_to_h2(v); }
   static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return h2_to_c32(ld_stream(p + i)); }
   static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, c32_to_h2(v)); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return c32_to_h2(v); }
@@ -358,6 +361,7 @@ __device__ __forceinline__ c32 cmul_dot2(h2 a, h2 b) {
 struct ModeF16MulF32Acc {
   typedef h2 Store; typedef h2 Lds; typedef c32 Comp; typedef h2 Tw; typedef h2 Filt;
   static __device__ __forceinline__ Comp decode(Store s) { return h2_to_c32(s); }
+  static __device__ __forceinline__ Store encode(Comp v) { return c32_to_h2(v); }
   static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return h2_to_c32(ld_stream(p + i)); }
   static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, c32_to_h2(v)); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return c32_to_h2(v); }
@@ -374,9 +378,10 @@ struct ModeFP8 {
     return c32{fp8_decode<MANT, BIAS>(b.x), fp8_decode<MANT, BIAS>(b.y)};
   }
   static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return decode(ld_stream(p + i)); }
-  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) {
-    st_stream(p + i, fp8x2{(uint8_t)fp8_encode<MANT, BIAS>(v.x), (uint8_t)fp8_encode<MANT, BIAS>(v.y)});
+  static __device__ __forceinline__ Store encode(Comp v) {
+    return fp8x2{(uint8_t)fp8_encode<MANT, BIAS>(v.x), (uint8_t)fp8_encode<MANT, BIAS>(v.y)};
   }
+  static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, encode(v)); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(v, w); }

@@ -14,6 +14,7 @@ enum Op { OP_FWD = 0, OP_INV = 1, OP_COMPRESS = 2 };
 enum KFlags : unsigned {
   KF_NAIVE = 1u,         // conventional post-scaling instead of the BFP fold
   KF_CHECK_FINITE = 2u,  // count non-finite outputs
+  KF_TRANSPOSED = 4u,    // compression: store out[k][row] (n x rows)
   KF_CONJ_FILTER = 16u,  // multiply by conj(filter)
 };
 
@@ -82,7 +83,7 @@ hipError_t launch_phasor(const float *phase, void *phasor, int n, int negate,
 // Autofocus: entropy statistics (S, Q, E), entropy gradient and the fused
 // adjoint + per-pulse phase-gradient reduction.
 constexpr int kEntropyBlocks = 1024;
-constexpr int kPhaseGradBlocks = 256;
+constexpr int kPhaseGradBlocks = 1024;  // 4 per CU on MI355X: the kernel needs the whole chip
 struct PhaseGradArgs {
   const void *gimg;      // FP32 pairs: dL/dI, or the image itself when fused
   const double *stats;   // (S, Q, E) when fused, else unused

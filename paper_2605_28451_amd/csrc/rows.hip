@@ -46,7 +46,18 @@ __device__ __forceinline__ h2 mul_c32(h2 v, c32 p) { return cmul(v, c32_to_h2(p)
 // Compile-time variants of the inverse / compression kernels (no runtime
 // selects in the per-element code): conventional post-scaling (debug),
 // conjugated filter (adjoint), per-pulse phasor at load.
-enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4 };
+enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4, V_TRANS = 8 };
+
+// Order of the row groups of a transposed store.  Workgroups are dispatched
+// to the 8 XCDs in turn (workgroup w on XCD w mod 8), so the groups of
+// iterations it = x, x + 8, ... (one XCD) are given consecutive rows: the
+// 4-byte stores that neighbouring rows make into one output line then meet
+// in that XCD's L2 instead of eight.  A bijection of [0, groups) (the
+// mapping only moves work; any dispatch order gives the same result).
+__device__ __forceinline__ int xcd_group(int it, int groups) {
+  const int q = groups >> 3, rem = groups & 7, x = it & 7, i = it >> 3;
+  return x * q + (x < rem ? x : rem) + i;
+}
 
 // PIPE (persistent grids, where the engine keeps its twiddles in registers):
 // the twiddle rows are loaded once per workgroup, and the next row group's
@@ -64,6 +75,9 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   constexpr bool naive = (V & V_NAIVE) != 0;
   constexpr bool conj_f = (V & V_CONJ) != 0;
   constexpr bool phasor = (V & V_PHASOR) != 0;
+  constexpr bool trans = (V & V_TRANS) != 0;
+  static_assert(!trans || (OP == OP_COMPRESS && V == V_TRANS && !OUT32),
+                "the transposed store is a variant of the plain compression");
 
   __shared__ typename M::Lds lds_all[G::TPW * G::LDS_N];
   // one transform per workgroup for N >= 4096: keep the row index uniform
@@ -89,10 +103,11 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   static_assert(!PIPE || EN::kTwRegs, "the pipelined kernel keeps its twiddles in registers");
   typename EN::TwRegs W;
   Store nx[PIPE ? E : 1];
+  auto group_of = [&](int it) { return trans ? xcd_group(it, groups) : it; };
   if constexpr (PIPE) {
     EN::load_tw_regs(tw, t, W);
-    const long long row0 = (long long)blockIdx.x * G::TPW + local;
-    if (row0 < a.rows) {
+    const long long row0 = (long long)group_of(blockIdx.x) * G::TPW + local;
+    if ((int)blockIdx.x < groups && row0 < a.rows) {
       const Store *src = static_cast<const Store *>(a.in) + row0 * N + t;
 #pragma unroll
       for (int e = 0; e < E; ++e) nx[e] = ld_stream(src + (unsigned)(T * e));
@@ -102,7 +117,8 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
     if constexpr (PIPE) EN::run_regs(x, lds, t, W);
     else EN::run(x, lds, tw, t);
   };
-  for (int grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+  for (int it = blockIdx.x; it < groups; it += gridDim.x) {
+  const int grp = group_of(it);
   const long long row = (long long)grp * G::TPW + local;
   const bool active = row < a.rows;
 
@@ -130,8 +146,9 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   }
   if constexpr (PIPE) {
     // the next group's data, in flight during this group's transforms
-    const long long nrow = row + (long long)gridDim.x * G::TPW;
-    if (grp + (int)gridDim.x < groups && nrow < a.rows) {
+    const int nit = it + (int)gridDim.x;
+    const long long nrow = nit < groups ? (long long)group_of(nit) * G::TPW + local : a.rows;
+    if (nrow < a.rows) {
       const Store *src = static_cast<const Store *>(a.in) + nrow * N + t;
 #pragma unroll
       for (int e = 0; e < E; ++e) nx[e] = ld_stream(src + (unsigned)(T * e));
@@ -170,7 +187,14 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   }
 
   if (active) {
-    if constexpr (OUT32) {
+    if constexpr (trans) {
+      // out[k][row] for k = t + T e: plain (cached) stores, so the rows of
+      // one output line merge in L2 before the line goes to HBM
+      Store *dst = static_cast<Store *>(a.out) + row + (long long)t * a.rows;
+      const long long step = (long long)T * a.rows;
+#pragma unroll
+      for (int e = 0; e < E; ++e) dst[e * step] = M::encode(v[e]);
+    } else if constexpr (OUT32) {
       c32 *dst = static_cast<c32 *>(a.out) + row * N + t;
 #pragma unroll
       for (int e = 0; e < E; ++e) st_stream(dst + (unsigned)(T * e), to_c32(v[e]));
@@ -313,7 +337,7 @@ static hipError_t launch_one(const RowArgs &a, hipStream_t s) {
   typedef Geometry<LOG2N> G;
   if (a.rows <= 0) return hipSuccess;
 #if BFP_MODE_ID == 3
-  if constexpr (LOG2N == 12) {
+  if constexpr (LOG2N == 12 && (V & V_TRANS) == 0) {
     if (a.engine == 0) return launch_mfma<OP, V, OUT32>(a, s);
   }
 #endif
@@ -346,6 +370,10 @@ static hipError_t launch_size(int op, bool out32, const RowArgs &a, hipStream_t 
       if (conj) return launch_one<LOG2N, OP_INV, V_CONJ, false>(a, s);
       return launch_one<LOG2N, OP_INV, V_PLAIN, false>(a, s);
     case OP_COMPRESS:
+      if (a.flags & KF_TRANSPOSED) {
+        if (naive || conj || ph || out32) return hipErrorInvalidValue;
+        return launch_one<LOG2N, OP_COMPRESS, V_TRANS, false>(a, s);
+      }
       if ((naive && (conj || ph)) || (conj && ph)) return hipErrorInvalidValue;
       if (naive) return out32 ? hipErrorInvalidValue : launch_one<LOG2N, OP_COMPRESS, V_NAIVE, false>(a, s);
       if (conj) return out32 ? hipErrorInvalidValue : launch_one<LOG2N, OP_COMPRESS, V_CONJ, false>(a, s);

@@ -6,7 +6,7 @@ import torch
 import oracle
 from paper_2605_28451_amd import metrics
 from paper_2605_28451_amd.metrics import sqnr_db
-from paper_2605_28451_amd import api, scenes
+from paper_2605_28451_amd import _lib, api, scenes
 from tests.gpu_util import announce, download, need_gpu, upload
 
 pytestmark = pytest.mark.gpu
@@ -71,6 +71,39 @@ def test_corner_turn_exact(fmt):
         x = scenes.quantize(0.1 * (rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))), fmt)
         y = download(api.corner_turn(upload(x, fmt), fmt), fmt)
         assert np.array_equal(y, x.T)
+
+
+@pytest.mark.parametrize("mode,n,rows", [("fp16", 4096, 300), ("fp16", 1024, 77), ("fp16", 4096, 4096),
+                                         ("fp32", 4096, 65), ("fp16_mul_fp32_acc", 4096, 40),
+                                         ("fp16_fp32", 512, 129), ("e4m3", 2048, 33)])
+def test_transposed_store_equals_corner_turn(mode, n, rows):
+    # the corner turn fused into the compression's store: bitwise the same
+    # as compressing row-major and transposing, for one-workgroup-per-row and
+    # persistent grids (the latter with the XCD-aware row order)
+    need_gpu()
+    announce(f"transposed store mode={mode} n={n} rows={rows}")
+    fmt = api.storage_format(mode)
+    sc = scenes.range_scene(seed=2, n_pulses=rows, n=n, length=n // 4)
+    x = upload(scenes.quantize(sc.echo, fmt), fmt)
+    H = api.filter_tensor(sc.replica, n, mode)
+    plan = api.FFTPlan(n, rows, mode)
+    ref = api.corner_turn(plan.range_compress(x, H), fmt)
+    engine, _ = plan.get_tuning()
+    for bpc in (0, 1, 3):
+        plan.set_tuning(engine, bpc)
+        got = plan.range_compress(x, H, transposed=True)
+        assert got.shape[:2] == (n, rows)
+        assert torch.equal(got, ref), f"blocks_per_cu={bpc}"
+
+
+def test_transposed_store_rejects_other_variants():
+    need_gpu()
+    plan = api.FFTPlan(1024, 8, "fp16")
+    H = api.filter_tensor(scenes.range_replica_padded(1024, 256), 1024, "fp16")
+    x = torch.zeros((8, 1024, 2), dtype=torch.float16, device="cuda")
+    for kw in ({"naive": True}, {"out_fp32": True}):
+        with pytest.raises(_lib.BfpError):
+            plan.range_compress(x, H, transposed=True, **kw)
 
 
 @pytest.mark.parametrize("src,dst", [("fp32", "fp16"), ("fp32", "e4m3"), ("fp32", "e5m2"),

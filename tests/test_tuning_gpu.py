@@ -26,8 +26,9 @@ def test_grid_size_does_not_change_results(mode, n):
     ref_f = plan.forward(x).clone()
     ref_c = plan.range_compress(x, H).clone()
     engine, bpc0 = plan.get_tuning()
-    assert (engine, bpc0) == (1, 0)  # a new plan: vector ALU, one workgroup per row group
-    for bpc in (1, 2, 8):
+    # a new plan: vector ALU, grid chosen per operation (-1)
+    assert (engine, bpc0) == (1, -1)
+    for bpc in (0, 1, 2, 8):
         plan.set_tuning(engine, bpc)
         assert plan.get_tuning() == (engine, bpc)
         assert torch.equal(plan.forward(x), ref_f)
@@ -53,7 +54,7 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     out = torch.empty_like(x)
     plan = api.FFTPlan(4096, 512, "fp16_mul_fp32_acc")
     e = autotune.tune(plan, "forward", x, out, reps=5)
-    assert e["ms"] > 0 and e["engine"] in (0, 1) and e["blocks_per_cu"] in (0, 1, 2, 3, 4, 5, 6, 8)
+    assert e["ms"] > 0 and e["engine"] in (0, 1) and e["blocks_per_cu"] in (-1, 0, 1, 2, 3, 4, 5, 6, 8)
     plan2 = api.FFTPlan(4096, 512, "fp16_mul_fp32_acc")
     assert autotune.apply_cached(plan2, "forward")
     assert plan2.get_tuning() == (e["engine"], e["blocks_per_cu"])
