@@ -136,7 +136,6 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
   constexpr int E = G::E, T = G::T, N = G::N;
   __shared__ c32 lds_all[G::TPW * G::LDS_N];
   const int local = threadIdx.x / T;
-  const int t = threadIdx.x & (T - 1);
   c32 *lds = lds_all + local * G::LDS_N;
   const c32 *tw = static_cast<const c32 *>(a.tw32);
   const StoreT *flt = static_cast<const StoreT *>(a.filter);
@@ -153,6 +152,12 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
   for (int e = 0; e < E; ++e) acc[e] = 0.0f;
   const int groups = (a.rows + G::TPW - 1) / G::TPW;
   for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+    // the thread index, made opaque per row: otherwise the compiler hoists
+    // every pass's LDS and twiddle addresses out of the loop into registers
+    // (the empty statement emits no instruction)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int t = tid & (T - 1);
     const long long row = (long long)g * G::TPW + local;
     const bool active = row < a.rows;
     c32 v[E];
@@ -179,6 +184,7 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
       }
     }
   }
+  const int t = threadIdx.x & (T - 1);
   float *dst = a.partial + ((long long)blockIdx.x * G::TPW + local) * N;
 #pragma unroll
   for (int e = 0; e < E; ++e) dst[t + T * e] = acc[e];

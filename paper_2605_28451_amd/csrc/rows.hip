@@ -113,14 +113,19 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
       for (int e = 0; e < E; ++e) nx[e] = ld_stream(src + (unsigned)(T * e));
     }
   }
-  auto transform = [&](Comp (&x)[E]) {
-    if constexpr (PIPE) EN::run_regs(x, lds, t, W);
-    else EN::run(x, lds, tw, t);
+  auto transform = [&](Comp (&x)[E], unsigned tt) {
+    if constexpr (PIPE) EN::run_regs(x, lds, tt, W);
+    else EN::run(x, lds, tw, tt);
   };
   for (int it = blockIdx.x; it < groups; it += gridDim.x) {
   const int grp = group_of(it);
   const long long row = (long long)grp * G::TPW + local;
   const bool active = row < a.rows;
+  // the thread index, made opaque per row group: otherwise the compiler
+  // hoists every pass's LDS addresses out of the loop into registers (the
+  // empty statement emits no instruction)
+  unsigned tt = t;
+  asm volatile("" : "+v"(tt));
 
   Comp v[E];
   if (active) {
@@ -129,7 +134,7 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
       for (int e = 0; e < E; ++e) v[e] = M::decode(nx[e]);
     } else {
       // one per-thread base, element offsets T e as immediates
-      const Store *src = static_cast<const Store *>(a.in) + row * N + t;
+      const Store *src = static_cast<const Store *>(a.in) + row * N + tt;
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = M::load(src, (unsigned)(T * e));
     }
@@ -139,7 +144,7 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   }
   if constexpr (OP == OP_COMPRESS && phasor) {
     if (active) {
-      const c32 *ph = static_cast<const c32 *>(a.phasor) + t;
+      const c32 *ph = static_cast<const c32 *>(a.phasor) + tt;
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = mul_c32(v[e], ph[T * e]);
     }
@@ -149,16 +154,16 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
     const int nit = it + (int)gridDim.x;
     const long long nrow = nit < groups ? (long long)group_of(nit) * G::TPW + local : a.rows;
     if (nrow < a.rows) {
-      const Store *src = static_cast<const Store *>(a.in) + nrow * N + t;
+      const Store *src = static_cast<const Store *>(a.in) + nrow * N + tt;
 #pragma unroll
       for (int e = 0; e < E; ++e) nx[e] = ld_stream(src + (unsigned)(T * e));
     }
   }
 
   if constexpr (OP == OP_FWD) {
-    transform(v);
+    transform(v, tt);
   } else {
-    if constexpr (OP == OP_COMPRESS) transform(v);
+    if constexpr (OP == OP_COMPRESS) transform(v, tt);
     // BFP fold at the inverse's load: conj(z . H) . 2^-log2N, or with the
     // conjugated filter conj(z . conj H) = conj(z) . H
     constexpr int K = naive ? 0 : LOG2N;  // block shift 2^-log2N
@@ -169,14 +174,14 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
       for (int e = 0; e < E; ++e) {
         Filt h;
         if constexpr (kHoist) h = hf[e];
-        else h = f[t + T * e];
+        else h = f[tt + T * e];
         v[e] = conj_f ? pow2<K>(M::fmul(cconj(v[e]), h)) : conj_pow2<K>(M::fmul(v[e], h));
       }
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = conj_pow2<K>(v[e]);
     }
-    transform(v);
+    transform(v, tt);
     if constexpr (naive) {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = pow2<LOG2N>(M::round_store(cconj(v[e])));
@@ -190,16 +195,16 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
     if constexpr (trans) {
       // out[k][row] for k = t + T e: plain (cached) stores, so the rows of
       // one output line merge in L2 before the line goes to HBM
-      Store *dst = static_cast<Store *>(a.out) + row + (long long)t * a.rows;
+      Store *dst = static_cast<Store *>(a.out) + row + (long long)tt * a.rows;
       const long long step = (long long)T * a.rows;
 #pragma unroll
       for (int e = 0; e < E; ++e) dst[e * step] = M::encode(v[e]);
     } else if constexpr (OUT32) {
-      c32 *dst = static_cast<c32 *>(a.out) + row * N + t;
+      c32 *dst = static_cast<c32 *>(a.out) + row * N + tt;
 #pragma unroll
       for (int e = 0; e < E; ++e) st_stream(dst + (unsigned)(T * e), to_c32(v[e]));
     } else {
-      Store *dst = static_cast<Store *>(a.out) + row * N + t;
+      Store *dst = static_cast<Store *>(a.out) + row * N + tt;
 #pragma unroll
       for (int e = 0; e < E; ++e) M::store(dst, (unsigned)(T * e), v[e]);
     }

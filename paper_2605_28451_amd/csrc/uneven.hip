@@ -38,15 +38,16 @@ constexpr int UNEVEN_WG = 1024;
 constexpr int UNEVEN_LDS = 16384 + 16384 / 16;  // largest per-item LDS (elements)
 
 template <class M, int LOG2N>
-__device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typename M::Lds *lds_all) {
+__device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typename M::Lds *lds_all,
+                                            int tid) {
   typedef Geometry<LOG2N> G;
   typedef Engine<M, LOG2N> EN;
   typedef typename M::Comp Comp;
   typedef typename M::Store Store;
   constexpr int E = G::E, T = G::T;
   static_assert((UNEVEN_WG / T) * G::LDS_N <= UNEVEN_LDS, "item exceeds LDS");
-  const int local = threadIdx.x / T;
-  const int t = threadIdx.x & (T - 1);
+  const int local = tid / T;
+  const int t = tid & (T - 1);
   const bool active = local < d.y;
   long long off = 0;
   bool inv = false;
@@ -95,14 +96,19 @@ __global__ void __launch_bounds__(UNEVEN_WG) uneven_kernel(UnevenArgs a) {
     __syncthreads();  // every thread has read item_s before it is rewritten
     if (it >= a.n_items) break;
     const int4 d = a.items[it];
+    // The thread index, made opaque per item: otherwise the compiler hoists
+    // the LDS and twiddle addresses of all seven sizes out of the loop and
+    // spills them (the empty statement emits no instruction).
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     switch (d.z) {
-      case 8: uneven_item<M, 8>(a, d, lds); break;
-      case 9: uneven_item<M, 9>(a, d, lds); break;
-      case 10: uneven_item<M, 10>(a, d, lds); break;
-      case 11: uneven_item<M, 11>(a, d, lds); break;
-      case 12: uneven_item<M, 12>(a, d, lds); break;
-      case 13: uneven_item<M, 13>(a, d, lds); break;
-      case 14: uneven_item<M, 14>(a, d, lds); break;
+      case 8: uneven_item<M, 8>(a, d, lds, tid); break;
+      case 9: uneven_item<M, 9>(a, d, lds, tid); break;
+      case 10: uneven_item<M, 10>(a, d, lds, tid); break;
+      case 11: uneven_item<M, 11>(a, d, lds, tid); break;
+      case 12: uneven_item<M, 12>(a, d, lds, tid); break;
+      case 13: uneven_item<M, 13>(a, d, lds, tid); break;
+      case 14: uneven_item<M, 14>(a, d, lds, tid); break;
       default: break;
     }
     __syncthreads();  // LDS of this item is free before the next one
