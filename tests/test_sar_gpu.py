@@ -66,11 +66,19 @@ def test_filter_matches_oracle_rounding():
 def test_corner_turn_exact(fmt):
     need_gpu()
     rng = np.random.default_rng(0)
-    for rows, cols in [(4096, 4096), (100, 260), (64, 1)]:
+    # vector form (both dims multiples of the chunk, full and ragged tiles),
+    # element form (odd shapes), and a misaligned view (element form)
+    for rows, cols in [(4096, 4096), (100, 260), (130, 66), (64, 1), (3, 5)]:
         announce(f"corner turn {rows}x{cols} {fmt}")
         x = scenes.quantize(0.1 * (rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))), fmt)
         y = download(api.corner_turn(upload(x, fmt), fmt), fmt)
         assert np.array_equal(y, x.T)
+    rows, cols = 128, 256
+    x = scenes.quantize(rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols)), fmt)
+    flat = upload(np.concatenate([np.zeros(1, complex), x.ravel()]), fmt)
+    view = flat[1:].view(rows, cols, *flat.shape[1:])
+    y = download(api.corner_turn(view, fmt), fmt)
+    assert np.array_equal(y, x.T)
 
 
 @pytest.mark.parametrize("mode,n,rows", [("fp16", 4096, 300), ("fp16", 1024, 77), ("fp16", 4096, 4096),
