@@ -52,8 +52,10 @@ __device__ __forceinline__ h2 csub(h2 a, h2 b) { return a - b; }
 __device__ __forceinline__ h2 csub_i(h2 a, h2 b) { return a + h2{b.y, -b.x}; }
 __device__ __forceinline__ h2 cadd_i(h2 a, h2 b) { return a + h2{-b.y, b.x}; }
 __device__ __forceinline__ h2 cmul(h2 a, h2 b) {
-  const h2 t = b * h2{a.x, a.x};                                // (ax bx, ax by)
-  return __builtin_elementwise_fma(h2{-a.y, a.y}, b.yx, t);     // + (-ay by, ay bx)
+  // a b = b.x (ax, ay) + b.y (-ay, ax): both products take b's halves as
+  // broadcasts and a's as a swizzle, all source modifiers of v_pk_fma_f16
+  const h2 t = a * h2{b.x, b.x};
+  return __builtin_elementwise_fma(h2{-a.y, a.x}, h2{b.y, b.y}, t);
 }
 __device__ __forceinline__ h2 cscale(h2 a, float s) { return a * h2{(f16)s, (f16)s}; }
 __device__ __forceinline__ h2 cconj(h2 a) { return h2{a.x, -a.y}; }

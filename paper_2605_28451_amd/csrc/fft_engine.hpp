@@ -178,11 +178,63 @@ struct Engine {
     if constexpr (G::S::P > 1) load_tw<1>(tw, t, W.w[0]);
     if constexpr (G::S::P > 2) load_tw<2>(tw, t, W.w[1]);
   }
-  static __device__ __forceinline__ void run_regs(Comp (&v)[E], Lds *lds, int t, TwRegs &W) {
+  // One pass with two alternating LDS buffers: exchange x (a count kept by
+  // the caller across passes, transforms and rows, uniform in the
+  // workgroup) writes buf[x & 1] and the next pass reads it back.  The
+  // previous reads of buf[x & 1] belong to the gather after exchange x - 2,
+  // which every wave finished before reaching the barrier of exchange x - 1,
+  // so one barrier per exchange (after the writes) orders everything.
+  template <int PASS>
+  static __device__ __forceinline__ void pass_db(Comp (&v)[E], Lds *const (&buf)[2], unsigned &x,
+                                                 int t, const Tw (&w)[E]) {
+    constexpr int R = G::radix(PASS);
+    constexpr int NS = G::span(PASS);
+    constexpr int B = E / R;
+    constexpr bool LAST = (PASS == G::S::P - 1);
+    if constexpr (PASS > 0) {
+      const Lds *rd = buf[(x - 1) & 1];
+      Lds raw[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) raw[e] = rd[lds_pad(t + T * e)];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        v[b] = M::from_lds(raw[b]);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[b + B * r] = M::twiddle(raw[b + B * r], w[b * R + r]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      Comp u[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[r] = v[b + B * r];
+      dft<R>(u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + B * r] = u[r];
+    }
+    if constexpr (!LAST) {
+      static_assert(pad_splits<R, NS>(), "padded offsets of a butterfly must not straddle a pad");
+      Lds *wr = buf[x & 1];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int j = t + T * b;
+        const int pbase = lds_pad((j / NS) * NS * R + (j & (NS - 1)));
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          wr[pbase + r * NS + ((r * NS) >> 4)] = M::to_lds(v[b + B * r]);
+      }
+      __syncthreads();
+      ++x;
+    }
+  }
+
+  // Forward transform with register twiddles and two LDS buffers.
+  static __device__ __forceinline__ void run_regs(Comp (&v)[E], Lds *const (&buf)[2], unsigned &x,
+                                                  int t, TwRegs &W) {
     static_assert(kTwRegs, "register twiddles need packed FP16 data and twiddles and at most 3 passes");
-    pass<0, false>(v, lds, nullptr, t, W.w[0]);
-    if constexpr (G::S::P > 1) pass<1, false>(v, lds, nullptr, t, W.w[0]);
-    if constexpr (G::S::P > 2) pass<2, false>(v, lds, nullptr, t, W.w[1]);
+    pass_db<0>(v, buf, x, t, W.w[0]);
+    if constexpr (G::S::P > 1) pass_db<1>(v, buf, x, t, W.w[0]);
+    if constexpr (G::S::P > 2) pass_db<2>(v, buf, x, t, W.w[1]);
   }
 };
 

@@ -79,11 +79,14 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   static_assert(!trans || (OP == OP_COMPRESS && V == V_TRANS && !OUT32),
                 "the transposed store is a variant of the plain compression");
 
-  __shared__ typename M::Lds lds_all[G::TPW * G::LDS_N];
+  // the pipelined kernel alternates two LDS buffers (one barrier per exchange)
+  __shared__ typename M::Lds lds_all[(PIPE ? 2 : 1) * G::TPW * G::LDS_N];
   // one transform per workgroup for N >= 4096: keep the row index uniform
   const int local = G::TPW == 1 ? 0 : (int)(threadIdx.x / T);
   const unsigned t = threadIdx.x & (T - 1);
   typename M::Lds *lds = lds_all + local * G::LDS_N;
+  typename M::Lds *const buf[2] = {lds, lds + (PIPE ? G::TPW * G::LDS_N : 0)};
+  unsigned xch = 0;  // LDS exchanges so far (pipelined kernel)
   const Tw *tw = static_cast<const Tw *>(a.tw);
   // A 4-byte filter (FP16 pairs) is the same for every row: its E values
   // per thread are loaded once, ahead of the row loop, so no row waits on
@@ -114,7 +117,7 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
     }
   }
   auto transform = [&](Comp (&x)[E], unsigned tt) {
-    if constexpr (PIPE) EN::run_regs(x, lds, tt, W);
+    if constexpr (PIPE) EN::run_regs(x, buf, xch, tt, W);
     else EN::run(x, lds, tw, tt);
   };
   for (int it = blockIdx.x; it < groups; it += gridDim.x) {

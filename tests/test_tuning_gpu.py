@@ -35,6 +35,28 @@ def test_grid_size_does_not_change_results(mode, n):
         assert torch.equal(plan.range_compress(x, H), ref_c)
 
 
+@pytest.mark.parametrize("n,rows", [(256, 333), (512, 101), (1024, 257), (2048, 130), (4096, 1029)])
+def test_pipelined_kernel_bitwise_equal(n, rows):
+    # pure FP16 up to n = 4096: a persistent grid runs the pipelined kernel
+    # (register twiddles, next group's data in flight); every operation must
+    # give the bits of the one-workgroup-per-group kernel, including ragged
+    # last groups (several transforms per workgroup below n = 4096) and grids
+    # smaller and larger than the group count
+    need_gpu()
+    announce(f"pipelined kernel fp16 n={n} rows={rows}")
+    sc = scenes.range_scene(seed=2, n_pulses=rows, n=n, length=n // 4)
+    x = upload(scenes.quantize(sc.echo, "fp16"), "fp16")
+    H = api.filter_tensor(sc.replica, n, "fp16")
+    plan = api.FFTPlan(n, rows, "fp16")
+    plan.set_tuning(1, 0)
+    ref = [plan.forward(x).clone(), plan.inverse_bfp(x, H).clone(), plan.range_compress(x, H).clone()]
+    for bpc in (1, 3, 64):
+        plan.set_tuning(1, bpc)
+        got = [plan.forward(x), plan.inverse_bfp(x, H), plan.range_compress(x, H)]
+        for name, a, b in zip(("forward", "inverse", "compress"), got, ref):
+            assert torch.equal(a, b), f"{name} blocks_per_cu={bpc}"
+
+
 def test_both_engines_meet_parity():
     need_gpu()
     x = scenes.quantize(scenes.gaussian_rows(1, 64, 4096), "fp16")
