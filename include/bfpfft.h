@@ -235,6 +235,18 @@ int sar_azimuth_compress(bfp_plan az_plan, const void *rc_t, void *image, const 
 int sar_image_entropy(bfp_plan plan, const void *image, long long count, double *stats,
                       void *stream);
 
+/* The image of sar_azimuth_compress (phase applied before the chain, output
+ * FP32 pairs) and its entropy statistics in one pass: each workgroup of the
+ * compression reduces |I|^2 and |I|^2 ln |I|^2 of the rows it wrote
+ * (FP32 logarithms, FP64 sums), and the workgroup partials are added in a
+ * fixed order into stats (device, 3 doubles as above).  The image is the
+ * one sar_azimuth_compress writes; the statistics agree with
+ * sar_image_entropy up to the order of the FP64 sums.  az_plan: precision
+ * BFP_FP32 or BFP_FP16_STORE_FP32_COMPUTE; n_range <= plan batch; calls on
+ * one plan must not overlap. */
+int sar_azimuth_image_entropy(bfp_plan az_plan, const void *rc_t, void *image, const void *h_az,
+                              const float *phase, int n_range, double *stats, void *stream);
+
 /* grad = scale . dE/dI as a real pair (dE/dRe I + i dE/dIm I)
  *      = scale . (-2/S)(ln p + E) I;  scale: (device) one float or NULL (1). */
 int sar_entropy_grad(const void *image, const double *stats, const float *scale, void *grad,

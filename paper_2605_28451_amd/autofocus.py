@@ -34,6 +34,24 @@ class AutofocusPlan(FFTPlan):
               "sar_image_entropy")
         return stats
 
+    def image_and_entropy(self, rc_t, h_az, phase, out=None, stats=None, stream=None):
+        """The image (FP32) and its entropy stats (S, Q, E) in one pass."""
+        rows = rc_t.numel() // (2 * self.n)
+        _check_storage(rc_t, self.fmt, rows * self.n, "rc_t")
+        _check_storage(h_az, self.filter_fmt, self.n, "filter")
+        if out is None:
+            out = torch.empty((rows, self.n, 2), dtype=torch.float32, device=rc_t.device)
+        _check_storage(out, "fp32", rows * self.n, "image")
+        if stats is None:
+            stats = torch.empty(3, dtype=torch.float64, device=rc_t.device)
+        if phase is not None and (phase.dtype != torch.float32 or phase.numel() != self.n
+                                  or not phase.is_cuda):
+            raise ValueError("phase: n_az float32 device values")
+        check(_lib.load().sar_azimuth_image_entropy(self._h, _ptr(rc_t), _ptr(out), _ptr(h_az),
+                                                    _ptr(phase), rows, _ptr(stats),
+                                                    _stream(stream)), "sar_azimuth_image_entropy")
+        return out, stats
+
     def entropy_grad(self, img, stats, scale=None, out=None, stream=None):
         count = img.numel() // 2
         if out is None:
@@ -93,7 +111,6 @@ class ImageEntropy(torch.autograd.Function):
 
 def entropy_and_grad(plan, rc_t, h_az, phase, img=None, stats=None, grad=None):
     """Fused path: (E as a device float64 scalar tensor, dE/dphase)."""
-    img = plan.image(rc_t, h_az, phase, out=img)
-    stats = plan.entropy_stats(img, stats)
+    img, stats = plan.image_and_entropy(rc_t, h_az, phase, out=img, stats=stats)
     grad = plan.phase_grad(rc_t, img, h_az, phase, stats=stats, out=grad)
     return stats[2], grad, img

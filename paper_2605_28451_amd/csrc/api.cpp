@@ -157,7 +157,8 @@ unsigned kflags(unsigned f) {
 }
 
 int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
-             const void *phasor, int rows, unsigned flags, void *stream) {
+             const void *phasor, int rows, unsigned flags, void *stream,
+             double *ent_partial = nullptr, int *grid_used = nullptr) {
   if (rows < 0 || rows > p->batch) return fail(BFP_EINVAL, "row count outside [0, plan batch]");
   if (rows == 0) return BFP_OK;
   if (!in || !out) return fail(BFP_EINVAL, "NULL data pointer");
@@ -175,6 +176,8 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   const int bpc = effective_bpc(p, op);
   a.grid_limit = bpc > 0 ? bpc * p->cu_count : 0;
   a.engine = p->tune_engine;
+  a.ent_partial = ent_partial;
+  if (grid_used) *grid_used = bfp::rows_grid(p->log2n, rows, a.grid_limit);
   const bool out32 = ((flags | p->flags) & BFP_FLAG_OUT_FP32) != 0;
   int cur = 0;
   (void)hipGetDevice(&cur);
@@ -289,7 +292,10 @@ int fft_plan(bfp_plan *out, int n, int batch, int prec, unsigned flags) {
     free_plan(p);
     return hip_fail(e, "hipMemset");
   }
-  if (hipMalloc((void **)&p->ent_partial, sizeof(double) * 2 * bfp::kEntropyBlocks) != hipSuccess) {
+  // entropy partials: the grid-stride reduction (kEntropyBlocks) or one
+  // per workgroup of a fused image launch (at most one per row)
+  if (hipMalloc((void **)&p->ent_partial,
+                sizeof(double) * 2 * (size_t)std::max(bfp::kEntropyBlocks, batch)) != hipSuccess) {
     free_plan(p);
     return fail(BFP_ENOMEM, "hipMalloc entropy workspace failed");
   }
@@ -444,6 +450,30 @@ int sar_image_entropy(bfp_plan plan, const void *image, long long count, double 
   if (count < 1) return fail(BFP_EINVAL, "count must be >= 1");
   if (!image || !stats) return fail(BFP_EINVAL, "NULL pointer");
   hipError_t e = bfp::launch_entropy(image, count, plan->ent_partial, stats, (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "entropy launch");
+}
+
+int sar_azimuth_image_entropy(bfp_plan az_plan, const void *rc_t, void *image, const void *h_az,
+                              const float *phase, int n_range, double *stats, void *stream) {
+  int st = check_rows_plan(az_plan);
+  if (st) return st;
+  if (az_plan->prec != BFP_FP32 && az_plan->prec != BFP_FP16_STORE_FP32_COMPUTE)
+    return fail(BFP_EUNSUPPORTED, "the fused image entropy runs in BFP_FP32 or BFP_FP16_STORE_FP32_COMPUTE");
+  if (!h_az || !stats) return fail(BFP_EINVAL, "NULL pointer");
+  if (n_range < 1 || n_range > az_plan->batch)
+    return fail(BFP_EINVAL, "n_range outside [1, plan batch]");
+  if (rc_t == image) return fail(BFP_EINVAL, "rc_t and image must differ");
+  const void *ph = nullptr;
+  if (phase) {
+    hipError_t e = bfp::launch_phasor(phase, az_plan->phasor, az_plan->n, 0, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "phasor launch");
+    ph = az_plan->phasor;
+  }
+  int grid = 0;
+  st = run_rows(az_plan, bfp::OP_COMPRESS, rc_t, image, h_az, ph, n_range, BFP_FLAG_OUT_FP32,
+                stream, az_plan->ent_partial, &grid);
+  if (st) return st;
+  hipError_t e = bfp::launch_entropy_final(az_plan->ent_partial, grid, stats, (hipStream_t)stream);
   return e == hipSuccess ? BFP_OK : hip_fail(e, "entropy launch");
 }
 

@@ -79,6 +79,12 @@ __global__ void __launch_bounds__(256) entropy_final_kernel(const double *__rest
   }
 }
 
+hipError_t launch_entropy_final(const double *partial, int blocks, double *stats, hipStream_t s) {
+  if (blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(entropy_final_kernel, dim3(1), dim3(256), 0, s, partial, blocks, stats);
+  return hipGetLastError();
+}
+
 hipError_t launch_entropy(const void *img, long long count, double *partial, double *stats,
                           hipStream_t s) {
   long long blocks = (count + 255) / 256;

@@ -29,7 +29,12 @@ struct RowArgs {
   unsigned long long *nonfinite;  // device counter
   int grid_limit;        // > 0: persistent grid of at most this many workgroups
   int engine;            // 0: matrix cores where available, 1: vector ALU only
+  double *ent_partial;   // compression to FP32 with phasor: per-workgroup (S, Q) of the
+                         // output's entropy sums (see rows_grid), or NULL
 };
+
+// Workgroups a row launch uses (what the per-workgroup partials count).
+int rows_grid(int log2n, int rows, int grid_limit);
 
 // whether (mode, size) has a matrix-core engine
 inline bool has_mfma_engine(int mode, int log2n) { return mode == 3 && log2n == 12; }
@@ -95,6 +100,8 @@ struct PhaseGradArgs {
   float *grad;           // n floats out
   int rows;
 };
+// (S, Q, E) from `blocks` partial (S, Q) pairs, summed in a fixed order.
+hipError_t launch_entropy_final(const double *partial, int blocks, double *stats, hipStream_t s);
 hipError_t launch_entropy(const void *img, long long count, double *partial, double *stats,
                           hipStream_t s);
 hipError_t launch_entropy_grad(const void *img, const double *stats, const float *scale, void *grad,

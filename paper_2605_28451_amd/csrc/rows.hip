@@ -46,7 +46,7 @@ __device__ __forceinline__ h2 mul_c32(h2 v, c32 p) { return cmul(v, c32_to_h2(p)
 // Compile-time variants of the inverse / compression kernels (no runtime
 // selects in the per-element code): conventional post-scaling (debug),
 // conjugated filter (adjoint), per-pulse phasor at load.
-enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4, V_TRANS = 8 };
+enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4, V_TRANS = 8, V_ENT = 16 };
 
 // Order of the row groups of a transposed store.  Workgroups are dispatched
 // to the 8 XCDs in turn (workgroup w on XCD w mod 8), so the groups of
@@ -78,6 +78,12 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   constexpr bool trans = (V & V_TRANS) != 0;
   static_assert(!trans || (OP == OP_COMPRESS && V == V_TRANS && !OUT32),
                 "the transposed store is a variant of the plain compression");
+  // entropy sums of the FP32 output (autofocus image): per workgroup
+  // S = sum |I|^2 and Q = sum |I|^2 ln |I|^2 over the rows it wrote
+  constexpr bool ent = (V & V_ENT) != 0;
+  static_assert(!ent || (OP == OP_COMPRESS && (V & ~V_PHASOR) == V_ENT && OUT32),
+                "entropy sums are a variant of the (phase-corrected) compression to FP32");
+  double es = 0.0, eq = 0.0;
 
   // the pipelined kernel alternates two LDS buffers (one barrier per exchange)
   __shared__ typename M::Lds lds_all[(PIPE ? 2 : 1) * G::TPW * G::LDS_N];
@@ -206,6 +212,15 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
       c32 *dst = static_cast<c32 *>(a.out) + row * N + tt;
 #pragma unroll
       for (int e = 0; e < E; ++e) st_stream(dst + (unsigned)(T * e), to_c32(v[e]));
+      if constexpr (ent) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const c32 z = to_c32(v[e]);
+          const float p = z.x * z.x + z.y * z.y;
+          es += p;
+          if (p > 0.0f) eq += (double)p * (double)logf(p);
+        }
+      }
     } else {
       Store *dst = static_cast<Store *>(a.out) + row * N + tt;
 #pragma unroll
@@ -222,6 +237,24 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
     }
   }
   }  // row groups
+  if constexpr (ent) {
+    // fixed-order tree over the workgroup; one (S, Q) per workgroup
+    __shared__ double esh[2][G::WG];
+    esh[0][threadIdx.x] = es;
+    esh[1][threadIdx.x] = eq;
+    __syncthreads();
+    for (int w = G::WG / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        esh[0][threadIdx.x] += esh[0][threadIdx.x + w];
+        esh[1][threadIdx.x] += esh[1][threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      a.ent_partial[2 * blockIdx.x] = esh[0][0];
+      a.ent_partial[2 * blockIdx.x + 1] = esh[1][0];
+    }
+  }
 }
 
 #if BFP_MODE_ID == 3
@@ -385,6 +418,15 @@ static hipError_t launch_size(int op, bool out32, const RowArgs &a, hipStream_t 
       if ((naive && (conj || ph)) || (conj && ph)) return hipErrorInvalidValue;
       if (naive) return out32 ? hipErrorInvalidValue : launch_one<LOG2N, OP_COMPRESS, V_NAIVE, false>(a, s);
       if (conj) return out32 ? hipErrorInvalidValue : launch_one<LOG2N, OP_COMPRESS, V_CONJ, false>(a, s);
+      if (a.ent_partial) {
+        if (!out32 || naive || conj) return hipErrorInvalidValue;
+#if BFP_MODE_ID == 0 || BFP_MODE_ID == 2
+        return ph ? launch_one<LOG2N, OP_COMPRESS, V_PHASOR | V_ENT, true>(a, s)
+                  : launch_one<LOG2N, OP_COMPRESS, V_ENT, true>(a, s);
+#else
+        return hipErrorInvalidValue;
+#endif
+      }
       if (ph)
         return out32 ? launch_one<LOG2N, OP_COMPRESS, V_PHASOR, true>(a, s)
                      : launch_one<LOG2N, OP_COMPRESS, V_PHASOR, false>(a, s);

@@ -102,3 +102,34 @@ def test_adjoint_dot_product_identity():
     ref = np.sum(np.imag(oracle.compress(y, H, conj_filter=True) * np.conj(z)), axis=0)
     got = ph.grad.cpu().numpy()
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("mode,with_phase,bpc", [("fp32", True, 0), ("fp16_fp32", True, 0),
+                                                 ("fp16_fp32", False, 0), ("fp16_fp32", True, 1)])
+def test_fused_image_entropy_matches_separate_passes(mode, with_phase, bpc):
+    # the image of the fused pass is the image of the azimuth compression,
+    # bit for bit; its statistics equal the separate reduction up to the
+    # order of the FP64 sums, and the entropy matches the FP64 oracle
+    need_gpu()
+    announce(f"fused image entropy mode={mode} phase={with_phase} bpc={bpc}")
+    sc, rc_t, phi = _small_case()
+    nr, npul = rc_t.shape
+    fmt = api.storage_format(mode)
+    rcq = scenes.quantize(rc_t, fmt)
+    plan = AutofocusPlan(npul, nr, mode)
+    plan.set_tuning(1, bpc)
+    Ha = api.filter_tensor(sc.azimuth_replica, npul, mode)
+    ph = torch.tensor(phi, dtype=torch.float32, device="cuda") if with_phase else None
+    rcd = upload(rcq, fmt)
+    img1 = plan.image(rcd, Ha, ph)
+    st1 = plan.entropy_stats(img1).cpu().numpy()
+    img2, st2 = plan.image_and_entropy(rcd, Ha, ph)
+    st2 = st2.cpu().numpy()
+    assert torch.equal(img1, img2)
+    assert abs(st2[0] - st1[0]) <= 1e-12 * st1[0]
+    assert abs(st2[1] - st1[1]) <= 1e-12 * abs(st1[1])
+    assert abs(st2[2] - st1[2]) <= 1e-10 * abs(st1[2])
+    Haq = scenes.quantize(oracle.matched_filter(sc.azimuth_replica, npul), api.filter_format(mode))
+    phi32 = phi.astype(np.float32).astype(np.float64) if with_phase else np.zeros(npul)
+    E_ref, _ = oracle.autofocus(rcq, Haq, phi32)
+    assert abs(st2[2] - E_ref) <= (1e-4 if mode == "fp32" else 2e-3) * abs(E_ref)
