@@ -205,7 +205,7 @@ def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30):
     return res
 
 
-def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30):
+def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30, inverse=False):
     import torch
     from paper_2605_28451_amd import api, scenes
     fmt = api.storage_format(mode)
@@ -216,8 +216,13 @@ def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30):
     ins = [x0 if i == 0 else x0.clone() for i in range(n_sets)]
     outs = [torch.empty_like(x0) for _ in range(n_sets)]
     plan = api.FFTPlan(n, rows, mode)
-    ms, total = time_launches(lambda i: plan.forward(ins[i], out=outs[i]), n_sets, steps, warmup)
-    res = {"mode": mode, "rows": rows, "n": n, "buffer_sets": n_sets, "ms_per_launch": ms,
+    if inverse:
+        launch = lambda i: plan.inverse_bfp(ins[i], out=outs[i])  # noqa: E731
+    else:
+        launch = lambda i: plan.forward(ins[i], out=outs[i])  # noqa: E731
+    ms, total = time_launches(launch, n_sets, steps, warmup)
+    res = {"mode": mode, "op": "inverse_bfp" if inverse else "forward", "rows": rows, "n": n,
+           "buffer_sets": n_sets, "ms_per_launch": ms,
            "gflops": fft_flops(n, rows) / (ms * 1e-3) / 1e9,
            "hbm_gbs": set_bytes / (ms * 1e-3) / 1e9}
     res["hbm_frac"] = res["hbm_gbs"] / HBM_PEAK_GBS
@@ -336,7 +341,8 @@ def bench_autofocus(steps, lr=0.3):
     plan = AutofocusPlan(n, n, mode)
     Ha = api.filter_tensor(sc.azimuth_replica, n, mode)
     phi = torch.zeros(n, dtype=torch.float32, device="cuda", requires_grad=True)
-    opt = torch.optim.Adam([phi], lr=lr)
+    # the fused Adam keeps its step count on the device: no host round trip per step
+    opt = torch.optim.Adam([phi], lr=lr, fused=True)
     img = torch.empty((n, n, 2), dtype=torch.float32, device="cuda")
     stats = torch.empty(3, dtype=torch.float64, device="cuda")
     grad = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -355,7 +361,16 @@ def bench_autofocus(steps, lr=0.3):
     ms = e0.elapsed_time(e1) / steps
     E, _, _ = entropy_and_grad(plan, rct, Ha, phi.detach(), img=img, stats=stats, grad=grad)
     img1 = api.to_host(img, "fp32")
-    return {"ms_per_step": ms, "steps": steps, "lr": lr, "entropy_before": E0,
+    # the image, entropy and phase gradient alone (no optimizer), back to back
+    ph = phi.detach()
+    e0.record()
+    for _ in range(steps):
+        entropy_and_grad(plan, rct, Ha, ph, img=img, stats=stats, grad=grad)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_grad = e0.elapsed_time(e1) / steps
+    return {"ms_per_step": ms, "ms_per_gradient": ms_grad, "steps": steps, "lr": lr,
+            "entropy_before": E0,
             "entropy_after": float(E), "_img0": img0, "_img1": img1, "_scene": sc}
 
 
@@ -493,6 +508,11 @@ def main():
             log(f"plain forward FFT n=4096 batch={b} mode={mode}")
             r = bench_fft(mode, b, n, args.steps, args.warmup)
             fft[mode] = {k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}
+        for name, inv in (("fp16_rows16384", False), ("fp16_inverse_bfp_rows16384", True)):
+            log(f"plain {'BFP inverse' if inv else 'forward'} FFT n=4096 batch=16384 mode=fp16 "
+                "(2 rotating sets, 1 GiB working set)")
+            r = bench_fft("fp16", 16384, n, args.steps, args.warmup, inverse=inv)
+            fft[name] = {k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}
         log("plain forward FFT n=4096 batch=64 (latency-bound shape)")
         r = bench_fft("fp16", 64, n, args.steps, args.warmup, min_bytes=0)
         fft["fp16_batch64"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}
@@ -532,7 +552,8 @@ def main():
         before = [_m.point_target(af["_img0"], r0, a0, search=64) for (r0, a0) in sc.targets]
         after = [_m.point_target(af["_img1"], r0, a0, search=64) for (r0, a0) in sc.targets]
         out["autofocus_4096"] = {
-            "ms_per_step": round(af["ms_per_step"], 4), "steps": af["steps"], "lr": af["lr"],
+            "ms_per_step": round(af["ms_per_step"], 4), "ms_per_gradient": round(af["ms_per_gradient"], 4),
+            "steps": af["steps"], "lr": af["lr"],
             "entropy_before": round(af["entropy_before"], 5), "entropy_after": round(af["entropy_after"], 5),
             "pslr_azimuth_db_before": round(float(np.mean([p["pslr_azimuth"] for p in before])), 2),
             "pslr_azimuth_db_after": round(float(np.mean([p["pslr_azimuth"] for p in after])), 2),
