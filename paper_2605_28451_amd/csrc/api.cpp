@@ -22,10 +22,10 @@ using bfp::RowArgs;
 namespace {
 
 // blocks_per_cu = kAutoBpc: the fused compression of pure FP16 up to n = 4096
-// runs the pipelined persistent kernel with 3 workgroups per CU (its
-// register budget allows 3 resident per CU; measured best at 2048 and 16384
-// rows of 4096); every other operation one workgroup per row group (the
-// single transforms are faster at full occupancy).
+// runs the pipelined persistent kernel with 3 workgroups per CU (4 fit, by
+// LDS; at 2048 rows of 4096, 3, 5 and 8 measure alike and 4 and 6 slower);
+// every other operation one workgroup per row group (the single transforms
+// are faster at full occupancy).
 constexpr int kAutoBpc = -1;
 constexpr int kPipelinedBpc = 3;
 

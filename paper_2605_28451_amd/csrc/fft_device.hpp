@@ -52,10 +52,13 @@ __device__ __forceinline__ h2 csub(h2 a, h2 b) { return a - b; }
 __device__ __forceinline__ h2 csub_i(h2 a, h2 b) { return a + h2{b.y, -b.x}; }
 __device__ __forceinline__ h2 cadd_i(h2 a, h2 b) { return a + h2{-b.y, b.x}; }
 __device__ __forceinline__ h2 cmul(h2 a, h2 b) {
-  // a b = b.x (ax, ay) + b.y (-ay, ax): both products take b's halves as
-  // broadcasts and a's as a swizzle, all source modifiers of v_pk_fma_f16
-  const h2 t = a * h2{b.x, b.x};
-  return __builtin_elementwise_fma(h2{-a.y, a.x}, h2{b.y, b.y}, t);
+  // a b = b.y (-ay, ax) + b.x (ax, ay): both products take b's halves as
+  // broadcasts and a's as a swizzle, all source modifiers of the packed
+  // instructions.  The swizzled product comes first: with register-held
+  // twiddles the compiler then needs no wait state between the two
+  // instructions (the other order costs one per product)
+  const h2 t = h2{-a.y, a.x} * h2{b.y, b.y};
+  return __builtin_elementwise_fma(a, h2{b.x, b.x}, t);
 }
 __device__ __forceinline__ h2 cscale(h2 a, float s) { return a * h2{(f16)s, (f16)s}; }
 __device__ __forceinline__ h2 cconj(h2 a) { return h2{a.x, -a.y}; }
@@ -95,6 +98,11 @@ __device__ __forceinline__ h2 pow2(h2 a) {
   if constexpr (K == 0) return a;
   else return pk_scale(a, h2{(f16)(1.0f / (1 << K)), (f16)(1.0f / (1 << K))});
 }
+// conj(a) as a sign flip (one instruction on a packed FP16 pair)
+__device__ __forceinline__ c32 conj_store(c32 a) { return c32{a.x, -a.y}; }
+__device__ __forceinline__ h2 conj_store(h2 a) {
+  return __builtin_bit_cast(h2, __builtin_bit_cast(uint32_t, a) ^ 0x80000000u);
+}
 // conj(a) . 2^-K
 template <int K>
 __device__ __forceinline__ c32 conj_pow2(c32 a) {
@@ -106,10 +114,6 @@ __device__ __forceinline__ h2 conj_pow2(h2 a) {
   static_assert(K >= 0 && K <= 14, "2^-K must be a normal FP16 number");
   if constexpr (K == 0) return h2{a.x, -a.y};
   else return pk_scale(a, h2{(f16)(1.0f / (1 << K)), (f16)(-1.0f / (1 << K))});
-}
-__device__ __forceinline__ c32 conj_store(c32 a) { return c32{a.x, -a.y}; }
-__device__ __forceinline__ h2 conj_store(h2 a) {
-  return __builtin_bit_cast(h2, __builtin_bit_cast(uint32_t, a) ^ 0x80000000u);
 }
 
 // ------------------------------------------------- radix constants ------
@@ -156,28 +160,44 @@ __device__ __forceinline__ C mulw(C a) {
 
 // ------------------------------------------------------------ DFTs ------
 // In-place length-R DFT (forward sign), natural order in and out.
-template <class C>
+// CJ = true returns the conjugated outputs: the last combining step takes
+// conjugated operands (conj(x + y) = conj x + conj y, conj(-i y) = i conj y),
+// which the packed adds apply as source negations, so the conjugate at the
+// end of an inverse transform costs no instruction.
+template <bool CJ = false, class C>
 __device__ __forceinline__ void dft2(C &a, C &b) {
-  C t = a;
-  a = cadd(t, b);
-  b = csub(t, b);
+  C t = CJ ? cconj(a) : a;
+  C u = CJ ? cconj(b) : b;
+  a = cadd(t, u);
+  b = csub(t, u);
 }
 
-template <class C>
+template <bool CJ = false, class C>
 __device__ __forceinline__ void dft4(C &a, C &b, C &c, C &d) {
   C s0 = cadd(a, c), s1 = csub(a, c), s2 = cadd(b, d), s3 = csub(b, d);
-  a = cadd(s0, s2);
-  c = csub(s0, s2);
-  b = csub_i(s1, s3);  // (a-c) - i(b-d)
-  d = cadd_i(s1, s3);  // (a-c) + i(b-d)
+  if constexpr (CJ) {
+    s0 = cconj(s0);
+    s1 = cconj(s1);
+    s2 = cconj(s2);
+    s3 = cconj(s3);
+    a = cadd(s0, s2);
+    c = csub(s0, s2);
+    b = cadd_i(s1, s3);  // conj((a-c) - i(b-d))
+    d = csub_i(s1, s3);  // conj((a-c) + i(b-d))
+  } else {
+    a = cadd(s0, s2);
+    c = csub(s0, s2);
+    b = csub_i(s1, s3);  // (a-c) - i(b-d)
+    d = cadd_i(s1, s3);  // (a-c) + i(b-d)
+  }
 }
 
-template <int R, class C>
+template <int R, bool CJ = false, class C>
 __device__ __forceinline__ void dft(C *v) {
   if constexpr (R == 2) {
-    dft2(v[0], v[1]);
+    dft2<CJ>(v[0], v[1]);
   } else if constexpr (R == 4) {
-    dft4(v[0], v[1], v[2], v[3]);
+    dft4<CJ>(v[0], v[1], v[2], v[3]);
   } else if constexpr (R == 8) {
     // n = n2 + 2 n1 (n2 < 2, n1 < 4), k = k1 + 4 k2
     dft4(v[0], v[2], v[4], v[6]);  // n2 = 0 -> slots 0,2,4,6 hold k1 = 0..3
@@ -188,8 +208,10 @@ __device__ __forceinline__ void dft(C *v) {
     C y[8];
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1) {
-      y[k1] = cadd(v[2 * k1], v[2 * k1 + 1]);
-      y[k1 + 4] = csub(v[2 * k1], v[2 * k1 + 1]);
+      const C p = CJ ? cconj(v[2 * k1]) : v[2 * k1];
+      const C q = CJ ? cconj(v[2 * k1 + 1]) : v[2 * k1 + 1];
+      y[k1] = cadd(p, q);
+      y[k1 + 4] = csub(p, q);
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = y[i];
@@ -209,7 +231,7 @@ __device__ __forceinline__ void dft(C *v) {
     v[14] = mulw<16, 6>(v[14]);
     v[15] = mulw<16, 9>(v[15]);
 #pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    for (int k1 = 0; k1 < 4; ++k1) dft4<CJ>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
     // slot k2 + 4 k1 holds X[k1 + 4 k2]: transpose the 4x4 slot grid
     C y[16];
 #pragma unroll

@@ -61,6 +61,23 @@ struct Geometry {
 
 __host__ __device__ __forceinline__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 
+// LDS slot of element t + T e.  T is a multiple of 16, so the pad of T e
+// is exact on its own: lds_pad(t + T e) = lds_pad(t) + T e + T e / 16, one
+// base register per thread and a compile-time offset per element.
+template <int T>
+__device__ __forceinline__ constexpr int lds_slot(int tpad, int e) {
+  static_assert(T % 16 == 0, "the pad split needs T to be a multiple of 16");
+  return tpad + T * e + ((T * e) >> 4);
+}
+
+// Padded LDS base of butterfly j's outputs in a Stockham pass of radix R and
+// span NS: position (j / NS) NS R + j mod NS (unsigned: shifts, no signed
+// division fix-up).
+template <int R, int NS>
+__device__ __forceinline__ int stockham_base(unsigned j) {
+  return lds_pad((int)((j / NS) * NS * R + (j & (NS - 1))));
+}
+
 // True when, for every butterfly j, lds_pad(base_j + r NS) equals
 // lds_pad(base_j) + r NS + (r NS) / 16, i.e. the low four bits of base_j
 // plus those of r NS never carry: then the R scattered writes of a
@@ -83,6 +100,14 @@ struct Engine {
   typedef typename M::Tw Tw;
   static constexpr int E = G::E;
   static constexpr int T = G::T;
+  // Conjugated outputs (CJ) are folded into the last pass when it ends in a
+  // DFT4 stage (radix 4 or 16), whose outputs are sums of sums: conj of a
+  // sum is then exactly the sum of conjugates.  A radix-2 or radix-8 last
+  // pass adds products, which the compiler may contract into FMAs
+  // differently once conjugates sit in between, so there the conjugate
+  // follows the transform and every kernel rounds alike.
+  static constexpr int kLastRadix = G::radix(G::S::P - 1);
+  static constexpr bool kFoldConj = kLastRadix == 4 || kLastRadix == 16;
 
   // Twiddle rows of pass PASS for this thread: butterfly b uses row
   // (t + T b) mod NS, entries r = 0..R-1, kept at w[b R + r].
@@ -108,7 +133,7 @@ struct Engine {
   // consumed its own, so their latency overlaps the butterflies and the LDS
   // exchange.  On exit v[e] holds the outputs (last pass) or the outputs
   // have been written to LDS.
-  template <int PASS, bool PREFETCH = true>
+  template <int PASS, bool PREFETCH = true, bool CJ = false>
   static __device__ __forceinline__ void pass(Comp (&v)[E], Lds *lds, const Tw *__restrict__ tw,
                                               int t, Tw (&w)[E]) {
     constexpr int R = G::radix(PASS);
@@ -117,8 +142,9 @@ struct Engine {
     constexpr bool LAST = (PASS == G::S::P - 1);
     if constexpr (PASS > 0) {
       Lds raw[E];
+      const int tp = lds_pad(t);
 #pragma unroll
-      for (int e = 0; e < E; ++e) raw[e] = lds[lds_pad(t + T * e)];
+      for (int e = 0; e < E; ++e) raw[e] = lds[lds_slot<T>(tp, e)];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         v[b] = M::from_lds(raw[b]);
@@ -132,7 +158,7 @@ struct Engine {
       Comp u[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) u[r] = v[b + B * r];
-      dft<R>(u);
+      dft<R, CJ && LAST && kFoldConj>(u);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b + B * r] = u[r];
     }
@@ -141,8 +167,7 @@ struct Engine {
       __syncthreads();  // all reads of the previous contents are done
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        const int j = t + T * b;
-        const int pbase = lds_pad((j / NS) * NS * R + (j & (NS - 1)));
+        const int pbase = stockham_base<R, NS>((unsigned)t + T * b);
         // lds_pad(base + r NS) = lds_pad(base) + r NS + (r NS) / 16 (see pad_splits)
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -152,15 +177,26 @@ struct Engine {
     }
   }
 
-  // Full forward transform: v[e] = x[t + T e] in, v[e] = X[t + T e] out.
+  // Full forward transform: v[e] = x[t + T e] in, v[e] = X[t + T e] out
+  // (CJ: conj(X[t + T e]), see kFoldConj).
+  template <bool CJ = false>
   static __device__ __forceinline__ void run(Comp (&v)[E], Lds *lds, const Tw *__restrict__ tw,
                                              int t) {
     Tw w[E];
     load_tw<1>(tw, t, w);
-    pass<0>(v, lds, tw, t, w);
-    if constexpr (G::S::P > 1) pass<1>(v, lds, tw, t, w);
-    if constexpr (G::S::P > 2) pass<2>(v, lds, tw, t, w);
-    if constexpr (G::S::P > 3) pass<3>(v, lds, tw, t, w);
+    pass<0, true, CJ>(v, lds, tw, t, w);
+    if constexpr (G::S::P > 1) pass<1, true, CJ>(v, lds, tw, t, w);
+    if constexpr (G::S::P > 2) pass<2, true, CJ>(v, lds, tw, t, w);
+    if constexpr (G::S::P > 3) pass<3, true, CJ>(v, lds, tw, t, w);
+    conj_unfolded<CJ>(v);
+  }
+
+  template <bool CJ>
+  static __device__ __forceinline__ void conj_unfolded(Comp (&v)[E]) {
+    if constexpr (CJ && !kFoldConj) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = conj_store(v[e]);
+    }
   }
 
   // ---- twiddles held in registers for a whole persistent kernel ----
@@ -184,7 +220,7 @@ struct Engine {
   // previous reads of buf[x & 1] belong to the gather after exchange x - 2,
   // which every wave finished before reaching the barrier of exchange x - 1,
   // so one barrier per exchange (after the writes) orders everything.
-  template <int PASS>
+  template <int PASS, bool CJ = false>
   static __device__ __forceinline__ void pass_db(Comp (&v)[E], Lds *const (&buf)[2], unsigned &x,
                                                  int t, const Tw (&w)[E]) {
     constexpr int R = G::radix(PASS);
@@ -194,8 +230,9 @@ struct Engine {
     if constexpr (PASS > 0) {
       const Lds *rd = buf[(x - 1) & 1];
       Lds raw[E];
+      const int tp = lds_pad(t);
 #pragma unroll
-      for (int e = 0; e < E; ++e) raw[e] = rd[lds_pad(t + T * e)];
+      for (int e = 0; e < E; ++e) raw[e] = rd[lds_slot<T>(tp, e)];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         v[b] = M::from_lds(raw[b]);
@@ -208,7 +245,7 @@ struct Engine {
       Comp u[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) u[r] = v[b + B * r];
-      dft<R>(u);
+      dft<R, CJ && LAST && kFoldConj>(u);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b + B * r] = u[r];
     }
@@ -217,8 +254,7 @@ struct Engine {
       Lds *wr = buf[x & 1];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        const int j = t + T * b;
-        const int pbase = lds_pad((j / NS) * NS * R + (j & (NS - 1)));
+        const int pbase = stockham_base<R, NS>((unsigned)t + T * b);
 #pragma unroll
         for (int r = 0; r < R; ++r)
           wr[pbase + r * NS + ((r * NS) >> 4)] = M::to_lds(v[b + B * r]);
@@ -228,13 +264,16 @@ struct Engine {
     }
   }
 
-  // Forward transform with register twiddles and two LDS buffers.
+  // Forward transform with register twiddles and two LDS buffers (CJ as in
+  // run).
+  template <bool CJ = false>
   static __device__ __forceinline__ void run_regs(Comp (&v)[E], Lds *const (&buf)[2], unsigned &x,
                                                   int t, TwRegs &W) {
     static_assert(kTwRegs, "register twiddles need packed FP16 data and twiddles and at most 3 passes");
-    pass_db<0>(v, buf, x, t, W.w[0]);
-    if constexpr (G::S::P > 1) pass_db<1>(v, buf, x, t, W.w[0]);
-    if constexpr (G::S::P > 2) pass_db<2>(v, buf, x, t, W.w[1]);
+    pass_db<0, CJ>(v, buf, x, t, W.w[0]);
+    if constexpr (G::S::P > 1) pass_db<1, CJ>(v, buf, x, t, W.w[0]);
+    if constexpr (G::S::P > 2) pass_db<2, CJ>(v, buf, x, t, W.w[1]);
+    conj_unfolded<CJ>(v);
   }
 };
 

@@ -126,6 +126,11 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
     if constexpr (PIPE) EN::run_regs(x, buf, xch, tt, W);
     else EN::run(x, lds, tw, tt);
   };
+  // the inverse's transform, its final conjugate folded into the last pass
+  auto transform_conj = [&](Comp (&x)[E], unsigned tt) {
+    if constexpr (PIPE) EN::template run_regs<true>(x, buf, xch, tt, W);
+    else EN::template run<true>(x, lds, tw, tt);
+  };
   for (int it = blockIdx.x; it < groups; it += gridDim.x) {
   const int grp = group_of(it);
   const long long row = (long long)grp * G::TPW + local;
@@ -135,6 +140,19 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   // empty statement emits no instruction)
   unsigned tt = t;
   asm volatile("" : "+v"(tt));
+  if constexpr (PIPE) {
+    // likewise the register twiddles and filter: hoisted, each FP16 pair
+    // would be kept twice, pre-broadcast as (re, re) and (im, im), instead
+    // of broadcast by the packed instructions' operand selects
+#pragma unroll
+    for (int p = 0; p < (int)(sizeof(W.w) / sizeof(W.w[0])); ++p)
+#pragma unroll
+      for (int e = 0; e < E; ++e) asm volatile("" : "+v"(W.w[p][e]));
+    if constexpr (kHoist) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) asm volatile("" : "+v"(hf[e]));
+    }
+  }
 
   Comp v[E];
   if (active) {
@@ -190,13 +208,12 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = conj_pow2<K>(v[e]);
     }
-    transform(v, tt);
     if constexpr (naive) {
+      transform(v, tt);
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = pow2<LOG2N>(M::round_store(cconj(v[e])));
     } else {
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = conj_store(v[e]);
+      transform_conj(v, tt);
     }
   }
 
