@@ -325,6 +325,32 @@ __device__ __forceinline__ void st_stream(T *p, T v) {
     __builtin_nontemporal_store(__builtin_bit_cast(u32x2, v), reinterpret_cast<u32x2 *>(p));
 }
 
+// The same through a pointer known to address global memory: a uniform base
+// can then stay in scalar registers (global loads and stores take a scalar
+// base, a 32-bit lane offset and an immediate).
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ T ld_stream_g(global_ptr<const T> p) {
+  static_assert(sizeof(T) == 2 || sizeof(T) == 4 || sizeof(T) == 8, "unsupported element size");
+  if constexpr (sizeof(T) == 2)
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<global_ptr<const uint16_t>>(p)));
+  else if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<global_ptr<const uint32_t>>(p)));
+  else
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<global_ptr<const u32x2>>(p)));
+}
+template <class T>
+__device__ __forceinline__ void st_stream_g(global_ptr<T> p, T v) {
+  static_assert(sizeof(T) == 2 || sizeof(T) == 4 || sizeof(T) == 8, "unsupported element size");
+  if constexpr (sizeof(T) == 2)
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<global_ptr<uint16_t>>(p));
+  else if constexpr (sizeof(T) == 4)
+    __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, v), reinterpret_cast<global_ptr<uint32_t>>(p));
+  else
+    __builtin_nontemporal_store(__builtin_bit_cast(u32x2, v), reinterpret_cast<global_ptr<u32x2>>(p));
+}
+
 // --------------------------------------------------- precision policies --
 // Each mode defines:
 //   Store: HBM element; Lds: on-chip element between passes;

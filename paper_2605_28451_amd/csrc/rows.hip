@@ -59,6 +59,39 @@ __device__ __forceinline__ int xcd_group(int it, int groups) {
   return x * q + (x < rem ? x : rem) + i;
 }
 
+// Elements t + T e of one row, raw (storage type).  With one transform per
+// workgroup the row's base is uniform: each group of four elements takes a
+// base in scalar registers and the immediates 0, T, 2T, 3T elements, so all
+// sixteen accesses share one 32-bit lane offset (ti, which must be < T).
+// (The pipelined kernel keeps per-lane pointers: there the compiler turns
+// this form into 64-bit address arithmetic per store.)
+template <class G, class X>
+__device__ __forceinline__ void load_row(X (&x)[G::E], const void *base, long long row, unsigned ti) {
+  static_assert(G::E % 4 == 0, "elements go in groups of four");
+  const X *src = static_cast<const X *>(base) + row * G::N;
+#pragma unroll
+  for (int e = 0; e < G::E; e += 4) {
+    const X *grp = src + G::T * e;
+    if constexpr (G::TPW == 1) asm volatile("" : "+s"(grp));
+    const global_ptr<const X> g = (global_ptr<const X>)grp;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[e + k] = ld_stream_g(g + (ti + (unsigned)(G::T * k)));
+  }
+}
+template <class G, class X>
+__device__ __forceinline__ void store_row(void *base, long long row, unsigned ti, const X (&x)[G::E]) {
+  static_assert(G::E % 4 == 0, "elements go in groups of four");
+  X *dst = static_cast<X *>(base) + row * G::N;
+#pragma unroll
+  for (int e = 0; e < G::E; e += 4) {
+    X *grp = dst + G::T * e;
+    if constexpr (G::TPW == 1) asm volatile("" : "+s"(grp));
+    const global_ptr<X> g = (global_ptr<X>)grp;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) st_stream_g(g + (ti + (unsigned)(G::T * k)), x[e + k]);
+  }
+}
+
 // PIPE (persistent grids, where the engine keeps its twiddles in registers):
 // the twiddle rows are loaded once per workgroup, and the next row group's
 // data is loaded into registers while the current group is transformed, so
@@ -98,6 +131,9 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   // per thread are loaded once, ahead of the row loop, so no row waits on
   // them.  Wider filters are read per row to keep registers free.
   const Filt *f = static_cast<const Filt *>(a.filter);
+  // row I/O through load_row / store_row (not in the pipelined kernel; FP8
+  // rows keep the per-element decode, which needs fewer registers)
+  constexpr bool kRowIo = !PIPE && sizeof(Store) >= 4;
   constexpr bool kHoist = sizeof(Filt) == 4 && OP != OP_FWD;
   Filt hf[kHoist ? E : 1];
   if constexpr (kHoist) {
@@ -160,10 +196,16 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = M::decode(nx[e]);
     } else {
-      // one per-thread base, element offsets T e as immediates
-      const Store *src = static_cast<const Store *>(a.in) + row * N + tt;
+      if constexpr (kRowIo) {
+        Store raw[E];
+        load_row<G>(raw, a.in, row, tt & (T - 1));
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = M::load(src, (unsigned)(T * e));
+        for (int e = 0; e < E; ++e) v[e] = M::decode(raw[e]);
+      } else {
+        const Store *src = static_cast<const Store *>(a.in) + row * N + tt;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = M::load(src, (unsigned)(T * e));
+      }
     }
   } else {
 #pragma unroll
@@ -226,9 +268,16 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) dst[e * step] = M::encode(v[e]);
     } else if constexpr (OUT32) {
-      c32 *dst = static_cast<c32 *>(a.out) + row * N + tt;
+      if constexpr (PIPE) {
+        c32 *dst = static_cast<c32 *>(a.out) + row * N + tt;
 #pragma unroll
-      for (int e = 0; e < E; ++e) st_stream(dst + (unsigned)(T * e), to_c32(v[e]));
+        for (int e = 0; e < E; ++e) st_stream(dst + (unsigned)(T * e), to_c32(v[e]));
+      } else {
+        c32 o[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) o[e] = to_c32(v[e]);
+        store_row<G>(a.out, row, tt & (T - 1), o);
+      }
       if constexpr (ent) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -239,9 +288,16 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
         }
       }
     } else {
-      Store *dst = static_cast<Store *>(a.out) + row * N + tt;
+      if constexpr (!kRowIo) {
+        Store *dst = static_cast<Store *>(a.out) + row * N + tt;
 #pragma unroll
-      for (int e = 0; e < E; ++e) M::store(dst, (unsigned)(T * e), v[e]);
+        for (int e = 0; e < E; ++e) M::store(dst, (unsigned)(T * e), v[e]);
+      } else {
+        Store o[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) o[e] = M::encode(v[e]);
+        store_row<G>(a.out, row, tt & (T - 1), o);
+      }
     }
     if (a.flags & KF_CHECK_FINITE) {
       unsigned bad = 0;
