@@ -9,6 +9,8 @@
 // items from a device counter until the queue is empty, so the load balances
 // across the 256 CUs without a second launch.  Every workgroup leaves the
 // loop when the counter passes the item count, so the grid always drains.
+#include <type_traits>
+
 #include "fft_engine.hpp"
 #include "internal.hpp"
 
@@ -85,8 +87,19 @@ __device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typenam
 template <class M>
 __global__ void uneven_reset_kernel(unsigned *queue) { *queue = 0u; }
 
+// Waves per SIMD the kernel is compiled for.  Pure FP16 fits two
+// 1024-thread workgroups per CU (8 waves per SIMD: 64 VGPRs, and 2 x 68 KiB
+// of LDS) without spills, so one workgroup's loads overlap the other's
+// arithmetic; compiled without the bound it takes 77 VGPRs (each size alone
+// needs at most 63) and one workgroup per CU.  The FP32-compute modes
+// would spill at 64, and the FP32 / FP8 modes' LDS holds one workgroup.
 template <class M>
-__global__ void __launch_bounds__(UNEVEN_WG) uneven_kernel(UnevenArgs a) {
+constexpr int uneven_waves_per_simd() {
+  return std::is_same<M, ModeFP16>::value ? 8 : 1;
+}
+
+template <class M>
+__global__ void __launch_bounds__(UNEVEN_WG, uneven_waves_per_simd<M>()) uneven_kernel(UnevenArgs a) {
   __shared__ typename M::Lds lds[UNEVEN_LDS];
   __shared__ int item_s;
   for (;;) {
