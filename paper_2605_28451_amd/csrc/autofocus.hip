@@ -32,10 +32,10 @@ __global__ void __launch_bounds__(256) entropy_partial_kernel(const c32 *__restr
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
     const c32 v = img[i];
-    // |I|^2 and its logarithm in FP32 (the image is FP32), sums in FP64
+    // |I|^2 and its logarithm in FP32 (the image is FP32; ln_pos), sums in FP64
     const float a = v.x * v.x + v.y * v.y;
     s += a;
-    if (a > 0.0f) q += (double)a * (double)logf(a);
+    q += (double)a * (double)ln_pos(a);  // 0 ln 0 = 0: ln_pos(0) is finite
   }
   sh[0][threadIdx.x] = s;
   sh[1][threadIdx.x] = q;
@@ -99,10 +99,10 @@ hipError_t launch_entropy(const void *img, long long count, double *partial, dou
 }
 
 // dE/dI scaled by an upstream factor: G = g (-2/S)(ln|I|^2 - ln S + E) I
+// (no branch: at I = 0 the factor is finite, since ln_pos is, and G = 0)
 __device__ __forceinline__ c32 entropy_grad_of(c32 v, double S, double E, float g) {
   const float a = v.x * v.x + v.y * v.y;
-  if (!(a > 0.0f)) return c32{0.0f, 0.0f};
-  const float c = (float)(-2.0 / S) * ((logf(a) - (float)log(S)) + (float)E) * g;
+  const float c = (float)(-2.0 / S) * ((ln_pos(a) - (float)log(S)) + (float)E) * g;
   return c32{c * v.x, c * v.y};
 }
 
@@ -128,12 +128,6 @@ hipError_t launch_entropy_grad(const void *img, const double *stats, const float
 }
 
 // ------------------------------------------------------ phase gradient ----
-template <class S>
-__device__ __forceinline__ c32 load_any(const S *p, size_t i);
-template <>
-__device__ __forceinline__ c32 load_any<c32>(const c32 *p, size_t i) { return p[i]; }
-template <>
-__device__ __forceinline__ c32 load_any<h2>(const h2 *p, size_t i) { return h2_to_c32(p[i]); }
 
 template <class StoreT, int LOG2N, bool FUSED>
 __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGradArgs a) {
@@ -141,7 +135,8 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
   typedef Engine<ModeFP32, LOG2N> EN;
   constexpr int E = G::E, T = G::T, N = G::N;
   __shared__ c32 lds_all[G::TPW * G::LDS_N];
-  const int local = threadIdx.x / T;
+  // one transform per workgroup for N >= 4096: keep the row index uniform
+  const int local = G::TPW == 1 ? 0 : (int)(threadIdx.x / T);
   c32 *lds = lds_all + local * G::LDS_N;
   const c32 *tw = static_cast<const c32 *>(a.tw32);
   const StoreT *flt = static_cast<const StoreT *>(a.filter);
@@ -166,26 +161,36 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
     const int t = tid & (T - 1);
     const long long row = (long long)g * G::TPW + local;
     const bool active = row < a.rows;
+    const unsigned ti = (unsigned)t;
     c32 v[E];
+    if (active) {
+      load_row<G>(v, gin, row, ti);
+      if constexpr (FUSED) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      c32 x = active ? gin[row * N + t + T * e] : c32{0.0f, 0.0f};
-      if constexpr (FUSED) x = entropy_grad_of(x, S, Ent, 1.0f);
-      v[e] = x;
+        for (int e = 0; e < E; ++e) v[e] = entropy_grad_of(v[e], S, Ent, 1.0f);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = c32{0.0f, 0.0f};
     }
     EN::run(v, lds, tw, t);
+    {
+      StoreT h[E];
+      load_row<G, false>(h, flt, 0, ti);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const c32 h = load_any<StoreT>(flt, t + T * e);
-      v[e] = conj_pow2<LOG2N>(cmul(v[e], cconj(h)));  // adjoint: conj(H_a), then the block shift
+      for (int e = 0; e < E; ++e)  // adjoint: conj(H_a), then the block shift
+        v[e] = conj_pow2<LOG2N>(cmul(v[e], cconj(to_c32(h[e]))));
     }
     EN::run(v, lds, tw, t);
     if (active) {
+      StoreT r[E];
+      c32 p[E];
+      load_row<G>(r, rc, row, ti);
+      load_row<G, false>(p, ph, 0, ti);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const c32 gz = cconj(v[e]);
-        const int m = t + T * e;
-        const c32 z = cmul(load_any<StoreT>(rc, row * N + m), ph[m]);
+        const c32 z = cmul(to_c32(r[e]), p[e]);
         acc[e] += gz.y * z.x - gz.x * z.y;  // Im(gz conj z)
       }
     }

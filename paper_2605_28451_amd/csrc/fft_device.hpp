@@ -341,6 +341,16 @@ __device__ __forceinline__ T ld_stream_g(global_ptr<const T> p) {
     return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<global_ptr<const u32x2>>(p)));
 }
 template <class T>
+__device__ __forceinline__ T ld_cached_g(global_ptr<const T> p) {
+  static_assert(sizeof(T) == 2 || sizeof(T) == 4 || sizeof(T) == 8, "unsupported element size");
+  if constexpr (sizeof(T) == 2)
+    return __builtin_bit_cast(T, *reinterpret_cast<global_ptr<const uint16_t>>(p));
+  else if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, *reinterpret_cast<global_ptr<const uint32_t>>(p));
+  else
+    return __builtin_bit_cast(T, *reinterpret_cast<global_ptr<const u32x2>>(p));
+}
+template <class T>
 __device__ __forceinline__ void st_stream_g(global_ptr<T> p, T v) {
   static_assert(sizeof(T) == 2 || sizeof(T) == 4 || sizeof(T) == 8, "unsupported element size");
   if constexpr (sizeof(T) == 2)
@@ -385,6 +395,16 @@ struct ModeFP16 {  // pure packed FP16
 };
 
 __device__ __forceinline__ c32 h2_to_c32(h2 v) { return c32{(float)v.x, (float)v.y}; }
+
+// Natural logarithm of a positive FP32 value from the hardware base-2
+// logarithm (v_log_f32, about 1 ulp) and one multiply, instead of the
+// library's correctly-scaled sequence (about 11 instructions more).  The
+// hardware instruction does not take denormal inputs, so arguments below the
+// smallest normal number are raised to it: for an image power p that small
+// the terms p ln p and p (ln p + c) are below 1e-36.
+__device__ __forceinline__ float ln_pos(float a) {
+  return __builtin_amdgcn_logf(fmaxf(a, 1.17549435e-38f)) * 0.693147180559945309f;
+}
 __device__ __forceinline__ h2 c32_to_h2(c32 v) { return h2{(f16)v.x, (f16)v.y}; }
 
 struct ModeF16StoreF32 {

@@ -92,6 +92,44 @@ constexpr bool pad_splits() {
   return true;
 }
 
+// Elements t + T e of one row, raw (storage type).  With one transform per
+// workgroup the row's base is uniform: each group of four elements takes a
+// base in scalar registers and the immediates 0, T, 2T, 3T elements, so all
+// sixteen accesses share one 32-bit lane offset (ti, which must be < T).
+// STREAM: nontemporal (row data read or written once); otherwise cached
+// (tables every row reads, such as a filter or a phasor: row = 0).
+// (The pipelined row kernel keeps per-lane pointers: there the compiler
+// turns this form into 64-bit address arithmetic per store.)
+template <class G, bool STREAM = true, class X>
+__device__ __forceinline__ void load_row(X (&x)[G::E], const void *base, long long row, unsigned ti) {
+  static_assert(G::E % 4 == 0, "elements go in groups of four");
+  const X *src = static_cast<const X *>(base) + row * G::N;
+#pragma unroll
+  for (int e = 0; e < G::E; e += 4) {
+    const X *grp = src + G::T * e;
+    if constexpr (G::TPW == 1) asm volatile("" : "+s"(grp));
+    const global_ptr<const X> g = (global_ptr<const X>)grp;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if constexpr (STREAM) x[e + k] = ld_stream_g(g + (ti + (unsigned)(G::T * k)));
+      else x[e + k] = ld_cached_g(g + (ti + (unsigned)(G::T * k)));
+    }
+  }
+}
+template <class G, class X>
+__device__ __forceinline__ void store_row(void *base, long long row, unsigned ti, const X (&x)[G::E]) {
+  static_assert(G::E % 4 == 0, "elements go in groups of four");
+  X *dst = static_cast<X *>(base) + row * G::N;
+#pragma unroll
+  for (int e = 0; e < G::E; e += 4) {
+    X *grp = dst + G::T * e;
+    if constexpr (G::TPW == 1) asm volatile("" : "+s"(grp));
+    const global_ptr<X> g = (global_ptr<X>)grp;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) st_stream_g(g + (ti + (unsigned)(G::T * k)), x[e + k]);
+  }
+}
+
 template <class M, int LOG2N>
 struct Engine {
   typedef Geometry<LOG2N> G;

@@ -59,39 +59,6 @@ __device__ __forceinline__ int xcd_group(int it, int groups) {
   return x * q + (x < rem ? x : rem) + i;
 }
 
-// Elements t + T e of one row, raw (storage type).  With one transform per
-// workgroup the row's base is uniform: each group of four elements takes a
-// base in scalar registers and the immediates 0, T, 2T, 3T elements, so all
-// sixteen accesses share one 32-bit lane offset (ti, which must be < T).
-// (The pipelined kernel keeps per-lane pointers: there the compiler turns
-// this form into 64-bit address arithmetic per store.)
-template <class G, class X>
-__device__ __forceinline__ void load_row(X (&x)[G::E], const void *base, long long row, unsigned ti) {
-  static_assert(G::E % 4 == 0, "elements go in groups of four");
-  const X *src = static_cast<const X *>(base) + row * G::N;
-#pragma unroll
-  for (int e = 0; e < G::E; e += 4) {
-    const X *grp = src + G::T * e;
-    if constexpr (G::TPW == 1) asm volatile("" : "+s"(grp));
-    const global_ptr<const X> g = (global_ptr<const X>)grp;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) x[e + k] = ld_stream_g(g + (ti + (unsigned)(G::T * k)));
-  }
-}
-template <class G, class X>
-__device__ __forceinline__ void store_row(void *base, long long row, unsigned ti, const X (&x)[G::E]) {
-  static_assert(G::E % 4 == 0, "elements go in groups of four");
-  X *dst = static_cast<X *>(base) + row * G::N;
-#pragma unroll
-  for (int e = 0; e < G::E; e += 4) {
-    X *grp = dst + G::T * e;
-    if constexpr (G::TPW == 1) asm volatile("" : "+s"(grp));
-    const global_ptr<X> g = (global_ptr<X>)grp;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) st_stream_g(g + (ti + (unsigned)(G::T * k)), x[e + k]);
-  }
-}
-
 // PIPE (persistent grids, where the engine keeps its twiddles in registers):
 // the twiddle rows are loaded once per workgroup, and the next row group's
 // data is loaded into registers while the current group is transformed, so
@@ -284,7 +251,7 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
           const c32 z = to_c32(v[e]);
           const float p = z.x * z.x + z.y * z.y;
           es += p;
-          if (p > 0.0f) eq += (double)p * (double)logf(p);
+          eq += (double)p * (double)ln_pos(p);  // 0 ln 0 = 0: ln_pos(0) is finite
         }
       }
     } else {
