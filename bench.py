@@ -418,6 +418,31 @@ def cpu_baseline(sample_in, replica, n, sample_out):
     }, sq, sq_raw
 
 
+def weighted_frame_metrics(mode, taper):
+    """Point-target metrics of one 4096x4096 frame whose range and azimuth
+    matched filters are weighted (taper: ("taylor", nbar, sll_db) or
+    ("hamming",)); the kernels are those of the timed frame, so only the
+    image quality is reported."""
+    import torch
+    from paper_2605_28451_amd import api, scenes, metrics
+    sc = scenes.sar_scene(seed=3)
+    n = 4096
+    fmt = api.storage_format(mode)
+    kind, rest = taper[0], taper[1:]
+    wl, wa = api.window(kind, 1024, *rest), api.window(kind, 512, *rest)
+    rplan = api.FFTPlan(n, n, mode)
+    aplan = api.FFTPlan(n, n, mode)
+    Hr = api.filter_tensor(scenes.weighted_range_replica(n, wl), n, mode)
+    Ha = api.filter_tensor(scenes.weighted_azimuth_replica(n, wa), n, mode)
+    rc = rplan.range_compress(api.to_device(sc.echo, fmt), Hr)
+    img = api.to_host(aplan.azimuth_compress(api.corner_turn(rc, fmt), Ha), fmt)
+    torch.cuda.synchronize()
+    rplan.close()
+    aplan.close()
+    return [metrics.point_target(img, r0, a0, noise_patch=(r0 + 300, a0 + 300))
+            for (r0, a0) in sc.targets]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -559,6 +584,18 @@ def main():
         out["sar_frame_4096"] = sar
         out["sar_frames_per_s_fp16"] = max(sar["fp16"]["frames_per_s"],
                                            sar["fp16_fused_corner_turn"]["frames_per_s"])
+        log("weighted SAR frames (Taylor nbar=5, -40 dB): image quality per mode")
+        wq = {"taper": "Taylor, nbar = 5, -40 dB, range (1024) and azimuth (512) filters"}
+        wpts = {m: weighted_frame_metrics(m, ("taylor", 5, 40.0))
+                for m in ("fp32", "fp16_fp32", "fp16_mul_fp32_acc", "fp16")}
+        for m, pts in wpts.items():
+            shift = max(max(abs(p[k] - q[k]) for k in ("pslr_range", "pslr_azimuth"))
+                        for p, q in zip(pts, wpts["fp32"]))
+            wq[m] = {"pslr_range_db_mean": round(float(np.mean([p["pslr_range"] for p in pts])), 3),
+                     "pslr_azimuth_db_mean": round(float(np.mean([p["pslr_azimuth"] for p in pts])), 3),
+                     "islr_range_db_mean": round(float(np.mean([p["islr_range"] for p in pts])), 3),
+                     "max_pslr_shift_vs_fp32_path_db": round(float(shift), 3)}
+        out["sar_frame_4096_weighted"] = wq
         log("uneven batch 20000 transforms fp16")
         ub = bench_uneven("fp16", args.steps, args.warmup)
         out["uneven_20000"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in ub.items()}

@@ -188,6 +188,22 @@ int fft_exec_uneven(bfp_plan p, const void *in, void *out, void *stream);
  * into (host) out_host[n]. */
 int bfp_make_filter(const double *h, int len, int n, int fmt, void *out_host);
 
+/* Amplitude taper for weighted apertures: the paper's limitations paragraph
+ * (Sec. VIII) names deeply weighted apertures (-40 dB sidelobes) as the case
+ * where the FP16 noise floor comes near and the FP32-accumulate mode is the
+ * remedy.  A weighted matched filter is bfp_make_filter of the replica
+ * multiplied point by point by this taper over the replica's support.
+ * Writes (host) out_host[len] in FP64, centred on the middle of the
+ * aperture:
+ *   BFP_WINDOW_RECT    1;
+ *   BFP_WINDOW_HAMMING 0.54 - 0.46 cos(2 pi n / (len - 1));
+ *   BFP_WINDOW_TAYLOR  Taylor taper with nbar terms whose nearest sidelobes
+ *                      sit near -sll_db dB (0 < sll_db <= 300, nbar >= 1),
+ *                      scaled to 1 at the aperture centre.
+ * nbar and sll_db are ignored for the other kinds.  Errors: BFP_EINVAL. */
+enum bfp_window_kind { BFP_WINDOW_RECT = 0, BFP_WINDOW_HAMMING = 1, BFP_WINDOW_TAYLOR = 2 };
+int bfp_window(int kind, int len, int nbar, double sll_db, double *out_host);
+
 /* Element-wise storage conversion of `count` complex values on the device,
  * rounding to nearest-even; FP8 targets saturate at their largest finite
  * value (E4M3: 448, E5M2: 57344).  in != out. */

@@ -62,6 +62,7 @@ SIGNATURES = {
     "fft_uneven_total": (_I, [_P, ctypes.POINTER(_LL)]),
     "fft_exec_uneven": (_I, [_P, _P, _P, _P]),
     "bfp_make_filter": (_I, [_P, _I, _I, _I, _P]),
+    "bfp_window": (_I, [_I, _I, _I, ctypes.c_double, _P]),
     "bfp_convert": (_I, [_P, _I, _P, _I, _LL, _P]),
     "bfp_device_copy": (_I, [_P, _P, _LL, _P]),
     "sar_range_compress": (_I, [_P, _P, _P, _P, _I, _U, _P]),

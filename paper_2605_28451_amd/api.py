@@ -71,6 +71,19 @@ def make_filter(replica: np.ndarray, n: int, fmt: str) -> np.ndarray:
     return out
 
 
+WINDOWS = {"rect": 0, "hamming": 1, "taylor": 2}
+
+
+def window(kind: str, length: int, nbar: int = 5, sll_db: float = 40.0) -> np.ndarray:
+    """Amplitude taper (host FP64) for weighted matched filters: 'rect',
+    'hamming' or 'taylor' (nbar terms, nearest sidelobes near -sll_db dB).
+    Multiply a replica by it over the replica's support before make_filter."""
+    out = np.empty(int(length), dtype=np.float64)
+    check(_lib.load().bfp_window(WINDOWS[kind], int(length), int(nbar), float(sll_db),
+                                 out.ctypes.data_as(ctypes.c_void_p)), "bfp_window")
+    return out
+
+
 def filter_tensor(replica, n: int, precision, device="cuda"):
     """The filter in the plan's filter format, on the device."""
     return torch.from_numpy(make_filter(replica, n, filter_format(precision))).to(device)

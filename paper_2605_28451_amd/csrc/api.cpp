@@ -372,6 +372,16 @@ int bfp_make_filter(const double *h, int len, int n, int fmt, void *out_host) {
   return BFP_OK;
 }
 
+int bfp_window(int kind, int len, int nbar, double sll_db, double *out_host) {
+  if (!out_host) return fail(BFP_EINVAL, "NULL argument");
+  if (len < 1) return fail(BFP_EINVAL, "window length must be >= 1");
+  if (kind < BFP_WINDOW_RECT || kind > BFP_WINDOW_TAYLOR) return fail(BFP_EINVAL, "unknown window kind");
+  if (kind == BFP_WINDOW_TAYLOR && (nbar < 1 || !(sll_db > 0.0) || sll_db > 300.0))
+    return fail(BFP_EINVAL, "Taylor window needs nbar >= 1 and 0 < sll_db <= 300");
+  if (!bfp::taper(kind, len, nbar, sll_db, out_host)) return fail(BFP_EINVAL, "bad window arguments");
+  return BFP_OK;
+}
+
 int bfp_convert(const void *in, int in_fmt, void *out, int out_fmt, long long count, void *stream) {
   if (count < 0) return fail(BFP_EINVAL, "count < 0");
   if (count == 0) return BFP_OK;

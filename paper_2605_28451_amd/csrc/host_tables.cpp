@@ -209,4 +209,57 @@ std::vector<uint16_t> mfma4096_table() {
   return t;
 }
 
+
+// Tapers for weighted apertures (Sec. VIII, limitations: deeply
+// weighted apertures aiming at -40 dB sidelobes).  Positions are centred on
+// the middle of the aperture, x_n = (n - (len - 1) / 2) / len.
+//
+// Hamming: 0.54 - 0.46 cos(2 pi n / (len - 1)).
+//
+// Taylor (nbar, SLL): with eta = 10^(SLL / 20), A = acosh(eta) / pi and the
+// dilation s^2 = nbar^2 / (A^2 + (nbar - 1/2)^2), the coefficients
+//   F_m = (-1)^(m+1) prod_{i<nbar} (1 - m^2 / (s^2 (A^2 + (i - 1/2)^2)))
+//         / (2 prod_{i<nbar, i != m} (1 - m^2 / i^2)),   m = 1 .. nbar - 1,
+// give w(x) = 1 + 2 sum_m F_m cos(2 pi m x), scaled to 1 at x = 0.  Its
+// first nbar - 1 sidelobes sit near -SLL dB; beyond them they fall as for
+// a uniform aperture.
+bool taper(int kind, int len, int nbar, double sll_db, double *out) {
+  if (!out || len < 1) return false;
+  if (kind == 0) {
+    for (int n = 0; n < len; ++n) out[n] = 1.0;
+    return true;
+  }
+  if (kind == 1) {
+    if (len == 1) {
+      out[0] = 1.0;
+      return true;
+    }
+    const double pi = 3.14159265358979323846;
+    for (int n = 0; n < len; ++n) out[n] = 0.54 - 0.46 * std::cos(2.0 * pi * n / (len - 1));
+    return true;
+  }
+  if (kind != 2 || nbar < 1 || !(sll_db > 0.0) || sll_db > 300.0) return false;
+  const double pi = 3.14159265358979323846;
+  const double eta = std::pow(10.0, sll_db / 20.0);
+  const double A = std::acosh(eta) / pi;
+  const double s2 = double(nbar) * nbar / (A * A + (nbar - 0.5) * (nbar - 0.5));
+  std::vector<double> F((size_t)nbar, 0.0);
+  for (int m = 1; m < nbar; ++m) {
+    double num = 1.0, den = 1.0;
+    for (int i = 1; i < nbar; ++i) {
+      num *= 1.0 - double(m) * m / (s2 * (A * A + (i - 0.5) * (i - 0.5)));
+      if (i != m) den *= 1.0 - double(m) * m / (double(i) * i);
+    }
+    F[m] = ((m % 2) ? 1.0 : -1.0) * num / (2.0 * den);
+  }
+  double centre = 1.0;
+  for (int m = 1; m < nbar; ++m) centre += 2.0 * F[m];
+  for (int n = 0; n < len; ++n) {
+    const double x = (n - 0.5 * (len - 1)) / len;
+    double w = 1.0;
+    for (int m = 1; m < nbar; ++m) w += 2.0 * F[m] * std::cos(2.0 * pi * m * x);
+    out[n] = w / centre;
+  }
+  return true;
+}
 }  // namespace bfp

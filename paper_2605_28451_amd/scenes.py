@@ -52,6 +52,29 @@ def range_replica_padded(n: int, length: int = 1024, b_num: int = 4, b_den: int 
     return h
 
 
+def weighted_range_replica(n: int, taper, length: int = 1024, b_num: int = 4,
+                           b_den: int = 5) -> np.ndarray:
+    """range_replica_padded with its `length` chirp samples multiplied by the
+    given taper (weighted matched filter; the echo itself is unweighted)."""
+    taper = np.asarray(taper, dtype=np.float64)
+    assert taper.shape == (length,)
+    h = range_replica_padded(n, length, b_num, b_den)
+    h[:length] *= taper
+    return h
+
+
+def weighted_azimuth_replica(n: int, taper, aperture: int = 512, b_num: int = 4,
+                             b_den: int = 5) -> np.ndarray:
+    """azimuth_replica_centred with sample m (-A/2 <= m < A/2) multiplied by
+    taper[m + A/2]."""
+    taper = np.asarray(taper, dtype=np.float64)
+    assert taper.shape == (aperture,)
+    g = azimuth_replica_centred(n, aperture, b_num, b_den)
+    m = np.arange(-aperture // 2, aperture // 2, dtype=np.int64)
+    g[m % n] *= taper
+    return g
+
+
 def awgn(rng, shape, snr_db: float) -> np.ndarray:
     p = 10.0 ** (-snr_db / 10.0)
     g = rng.standard_normal((2,) + tuple(shape))

@@ -76,3 +76,17 @@ def test_make_filter_rejects_bad_sizes():
         api.make_filter(np.ones(20), 16, "fp16")
     with pytest.raises(_lib.BfpError):
         api.make_filter(np.zeros(8), 16, "fp16")
+
+
+def test_library_tapers_match_oracle():
+    # bfp_window (host FP64) against the oracle's independent tapers
+    from oracle import windows as W
+    for length in (1, 2, 16, 127, 512, 1024):
+        assert np.all(api.window("rect", length) == 1.0)
+        assert np.max(np.abs(api.window("hamming", length) - W.hamming(length))) <= 1e-14
+        for nbar, sll in ((1, 30.0), (4, 30.0), (5, 40.0), (8, 50.0)):
+            got = api.window("taylor", length, nbar, sll)
+            assert np.max(np.abs(got - W.taylor(length, nbar, sll))) <= 1e-13, (length, nbar, sll)
+    for bad in ((2, 16, 0, 40.0), (2, 16, 5, 0.0), (2, 0, 5, 40.0), (3, 16, 5, 40.0)):
+        out = np.empty(16)
+        assert _lib.load().bfp_window(*bad, out.ctypes.data_as(ctypes.c_void_p)) == _lib.EINVAL

@@ -235,3 +235,62 @@ def test_autofocus_gradient_fd_and_invariance():
         pm = phi.copy(); pm[m] -= h
         fd = (oracle.autofocus(rc, Ha, pp)[0] - oracle.autofocus(rc, Ha, pm)[0]) / (2 * h)
         assert fd == pytest.approx(g[m], rel=1e-6, abs=1e-10)
+
+
+# ---------------------------------------------------- weighted apertures ----
+# Tapers for the weighted matched filters of Sec. VIII (limitations: deeply
+# weighted apertures with sidelobes near -40 dB).  Pins: the library routine
+# scipy.signal.windows, and closed-form facts of the tapers' transforms.
+
+def _transform_pslr(w, pad=64):
+    """Highest sidelobe of |DFT(w)|^2 (zero-padded) outside the first minima."""
+    P = np.fft.fftshift(np.abs(np.fft.fft(w, w.size * pad)) ** 2)
+    k = int(np.argmax(P))
+    lo, hi = k, k
+    while lo > 0 and P[lo - 1] < P[lo]:
+        lo -= 1
+    while hi < P.size - 1 and P[hi + 1] < P[hi]:
+        hi += 1
+    return 10.0 * np.log10(np.concatenate([P[:lo], P[hi + 1:]]).max() / P[k])
+
+
+@pytest.mark.parametrize("length", [1, 2, 16, 127, 1024])
+def test_tapers_match_scipy(length):
+    from scipy.signal import windows as sw
+    from oracle import windows as W
+    assert np.max(np.abs(W.hamming(length) - sw.hamming(length, sym=True))) <= 1e-14
+    for nbar, sll in ((1, 30.0), (4, 30.0), (5, 40.0), (8, 50.0)):
+        want = sw.taylor(length, nbar, sll, norm=True, sym=True)
+        assert np.max(np.abs(W.taylor(length, nbar, sll) - want)) <= 1e-13, (nbar, sll)
+
+
+def test_taper_sidelobes_closed_form():
+    from oracle import windows as W
+    # uniform aperture: -13.26 dB; Hamming 0.54 / 0.46: -42.7 dB
+    assert abs(_transform_pslr(np.ones(1024)) + 13.26) <= 0.05
+    assert abs(_transform_pslr(W.hamming(1024)) + 42.7) <= 0.1
+    # Taylor: the nearest sidelobes at the design level
+    for nbar, sll in ((4, 30.0), (5, 40.0), (8, 50.0)):
+        assert abs(_transform_pslr(W.taylor(1024, nbar, sll)) + sll) <= 0.4, (nbar, sll)
+
+
+def test_weighted_point_target_sidelobes_and_broadening():
+    # the oracle's range compression of an LFM target (L = 1024, b = 0.8)
+    # with a weighted filter: sidelobes at the taper's level (the chirp's
+    # spectrum is nearly flat over its band), and the Hamming -3 dB width
+    # 1.47 times the uniform one (1.30 / 0.886 bins)
+    from oracle import windows as W
+    from paper_2605_28451_amd import metrics
+    n = 4096
+    x = np.zeros((1, n), dtype=np.complex128)
+    x[0, :1024] = scenes.lfm_chirp(1024)
+    res = {}
+    for name, w in (("rect", np.ones(1024)), ("hamming", W.hamming(1024)),
+                    ("taylor", W.taylor(1024, 5, 40.0))):
+        H = oracle.matched_filter(scenes.weighted_range_replica(n, w), n)
+        res[name] = metrics.cut_metrics_1d(oracle.compress(x, H)[0])
+    assert abs(res["rect"][0] + 13.26) <= 0.1
+    assert abs(res["hamming"][0] + 42.7) <= 0.3
+    assert abs(res["taylor"][0] + 40.0) <= 0.7
+    assert abs(res["hamming"][2] / res["rect"][2] - 1.47) <= 0.03
+    assert res["rect"][2] < res["taylor"][2] < res["hamming"][2]

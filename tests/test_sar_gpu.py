@@ -191,6 +191,64 @@ def test_sar_frame_4096_matches_oracle_metrics(mode):
             assert abs(mg[k] - mo[k]) <= 0.02, (r0, a0, k, mg[k], mo[k])
 
 
+def _weighted_frames(sc, mode, taper):
+    """GPU frame with filters tapered by the library's bfp_window, and the
+    oracle frame with the oracle's own tapers (same scene, same storage)."""
+    from oracle import windows as W
+    npul, nr = sc.echo.shape
+    fmt, ffmt = api.storage_format(mode), api.filter_format(mode)
+    if taper == "taylor":
+        wl, wa = api.window("taylor", 1024, 5, 40.0), api.window("taylor", 512, 5, 40.0)
+        ol, oa = W.taylor(1024, 5, 40.0), W.taylor(512, 5, 40.0)
+    else:
+        wl, wa = api.window("hamming", 1024), api.window("hamming", 512)
+        ol, oa = W.hamming(1024), W.hamming(512)
+    rplan = api.FFTPlan(nr, npul, mode, flags=api.FLAG_CHECK_FINITE)
+    aplan = api.FFTPlan(npul, nr, mode, flags=api.FLAG_CHECK_FINITE)
+    Hr = api.filter_tensor(scenes.weighted_range_replica(nr, wl), nr, mode)
+    Ha = api.filter_tensor(scenes.weighted_azimuth_replica(npul, wa), npul, mode)
+    rc = rplan.range_compress(upload(scenes.quantize(sc.echo, fmt), fmt), Hr)
+    img = download(aplan.azimuth_compress(api.corner_turn(rc, fmt), Ha), fmt)
+    assert rplan.nonfinite() == 0 and aplan.nonfinite() == 0
+    Hro = scenes.quantize(oracle.matched_filter(scenes.weighted_range_replica(nr, ol), nr), ffmt)
+    Hao = scenes.quantize(oracle.matched_filter(scenes.weighted_azimuth_replica(npul, oa), npul), ffmt)
+    ref = oracle.sar_image(scenes.quantize(sc.echo, fmt), Hro, Hao)
+    return img, ref
+
+
+# Weighted apertures (Sec. VIII, limitations): with -40 dB Taylor sidelobes
+# the modes that accumulate in FP32 keep PSLR/ISLR/SNR within 0.1 dB of the
+# FP64 oracle; pure FP16 moves the Taylor PSLR by up to about 0.15 dB
+# (measured 0.14 dB), the approach to the FP16 floor the paper anticipates,
+# so its PSLR bar here is 0.25 dB (ISLR, SNR and IRW still at 0.1 dB /
+# 0.02 samples).
+@pytest.mark.parametrize("mode,taper", [("fp32", "taylor"), ("fp16_fp32", "taylor"),
+                                        ("fp16_mul_fp32_acc", "taylor"), ("fp16", "taylor"),
+                                        ("fp16_mul_fp32_acc", "hamming"), ("fp16", "hamming")])
+def test_weighted_frame_4096_matches_oracle_metrics(mode, taper):
+    need_gpu()
+    announce(f"weighted SAR frame 4096x4096 mode={mode} taper={taper}")
+    sc = scenes.sar_scene(seed=3)
+    img, ref = _weighted_frames(sc, mode, taper)
+    assert np.all(np.isfinite(img))
+    pslr_bar = 0.25 if mode == "fp16" else 0.1
+    worst = 0.0
+    for (r0, a0) in sc.targets:
+        mg = metrics.point_target(img, r0, a0, noise_patch=(r0 + 300, a0 + 300))
+        mo = metrics.point_target(ref, r0, a0, noise_patch=(r0 + 300, a0 + 300))
+        assert mg["peak_rc"] == mo["peak_rc"] == (r0, a0)
+        # the taper is in effect: sidelobes near its design level
+        assert mo["pslr_range"] < (-39.0 if taper == "taylor" else -42.0)
+        for k in ("pslr_range", "pslr_azimuth"):
+            worst = max(worst, abs(mg[k] - mo[k]))
+            assert abs(mg[k] - mo[k]) <= pslr_bar, (r0, a0, k, mg[k], mo[k])
+        for k in ("islr_range", "islr_azimuth", "snr"):
+            assert abs(mg[k] - mo[k]) <= 0.1, (r0, a0, k, mg[k], mo[k])
+        for k in ("irw_range", "irw_azimuth"):
+            assert abs(mg[k] - mo[k]) <= 0.02, (r0, a0, k, mg[k], mo[k])
+    print(f"mode={mode} taper={taper} worst PSLR shift {worst:.3f} dB")
+
+
 def test_azimuth_phase_correction_matches_oracle():
     need_gpu()
     sc = scenes.sar_scene(seed=3, n=1024, length=256, aperture=128, ranges=(300,), azimuths=(512,))

@@ -74,3 +74,17 @@ def test_scenes_are_seeded_and_shaped():
     assert abs(phi[2048 + 256] - phi[2048] - 4 * np.pi) < 3.0
     sc = scenes.sar_scene(seed=3, n=512, ranges=(100,), azimuths=(256,), length=64, aperture=32)
     assert sc.echo.shape == (512, 512) and sc.targets == [(100, 256)]
+
+
+def test_weighted_replicas_taper_the_support_only():
+    n = 4096
+    w = np.linspace(0.5, 1.0, 1024)
+    h = scenes.weighted_range_replica(n, w)
+    h0 = scenes.range_replica_padded(n)
+    assert np.array_equal(h[:1024], h0[:1024] * w) and not np.any(h[1024:])
+    wa = np.linspace(0.25, 1.0, 512)
+    g = scenes.weighted_azimuth_replica(n, wa)
+    g0 = scenes.azimuth_replica_centred(n)
+    m = np.arange(-256, 256)
+    assert np.array_equal(g[m % n], g0[m % n] * wa)
+    assert np.count_nonzero(g) == 512
