@@ -11,8 +11,8 @@
 // pass reads thread t's inputs from positions t + T e (e = 0..E-1), so the
 // first pass reads HBM and the last pass writes HBM with unit stride across
 // the threads of a wavefront (coalesced), and only the interior passes touch
-// LDS.  The LDS index is padded by one element per 16 to keep the scattered
-// Stockham writes free of bank conflicts.
+// LDS.  Each exchange has its own padded layout (Pad) that keeps both the
+// scattered Stockham writes and the reads free of bank conflicts.
 //
 // Twiddles come from a per-plan table in HBM (L2/L1-resident after the first
 // wavefronts): pass p owns NS_p x R_p entries W_{NS R}^{m r}, m < NS, r < R,
@@ -33,6 +33,22 @@ template <> struct Shape<12> { static constexpr int E = 16, P = 3, R0 = 16, R1 =
 template <> struct Shape<13> { static constexpr int E = 16, P = 4, R0 = 16, R1 = 16, R2 = 16, R3 = 2; };
 template <> struct Shape<14> { static constexpr int E = 16, P = 4, R0 = 16, R1 = 16, R2 = 16, R3 = 4; };
 
+// LDS layout of exchange X (written by pass X, read by pass X + 1): element
+// i sits at slot i + C (i >> S).  Each half-wavefront's 32 lanes then hit 32
+// different banks both in the Stockham scatter of pass X and in the reads at
+// t + T e of pass X + 1 (checked by simulation for every size; the bank
+// conflict counter confirms 32 banks per half-wavefront): after a span-1
+// pass, (C, S) = (1, 5); after a span-16 radix-16 pass, (4, 6) ((8, 6) after
+// span 8 at N = 512); after a span-256 pass the scatter is conflict-free
+// unpadded (C = 0).  N = 256 (four transforms per wavefront) keeps one pad
+// slot per 16.  One pad slot per 16 in every exchange made each read 2-way.
+template <int LOG2N, int X>
+struct Pad {
+  static constexpr int C = LOG2N == 8 ? 1 : X == 0 ? 1 : X == 1 ? (LOG2N == 9 ? 8 : 4) : 0;
+  static constexpr int S = LOG2N == 8 ? 4 : X == 0 ? 5 : 6;
+  static __host__ __device__ constexpr int at(int i) { return i + C * (i >> S); }
+};
+
 template <int LOG2N>
 struct Geometry {
   typedef Shape<LOG2N> S;
@@ -41,7 +57,16 @@ struct Geometry {
   static constexpr int T = N / E;                    // threads per transform
   static constexpr int WG = T < 256 ? 256 : T;       // threads per workgroup
   static constexpr int TPW = WG / T;                 // transforms per workgroup
-  static constexpr int LDS_N = N + N / 16;           // padded LDS elements
+  // padded LDS elements: the largest exchange layout, at least N + N / 16
+  static constexpr int LDS_N = [] {
+    int m = N + N / 16;
+    for (int x = 0; x + 1 < S::P; ++x) {
+      const int slots = (x == 0 ? Pad<LOG2N, 0>::at(N - 1)
+                         : x == 1 ? Pad<LOG2N, 1>::at(N - 1) : Pad<LOG2N, 2>::at(N - 1)) + 1;
+      m = slots > m ? slots : m;
+    }
+    return m;
+  }();
   static constexpr int radix(int p) {
     return p == 0 ? S::R0 : p == 1 ? S::R1 : p == 2 ? S::R2 : S::R3;
   }
@@ -59,35 +84,38 @@ struct Geometry {
   static constexpr int tw_entries() { return tw_offset(S::P); }
 };
 
-__host__ __device__ __forceinline__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+// Offset of element d in a layout, relative to a base whose position is a
+// multiple of 2^S or whose low bits never carry into bit S with d (see
+// pad_splits): d + C (d >> S).
+template <class P>
+__host__ __device__ constexpr int pad_off(int d) { return d + P::C * (d >> P::S); }
 
-// LDS slot of element t + T e.  T is a multiple of 16, so the pad of T e
-// is exact on its own: lds_pad(t + T e) = lds_pad(t) + T e + T e / 16, one
-// base register per thread and a compile-time offset per element.
-template <int T>
+// Slot of element t + T e in layout P.  T is a multiple of 2^S (or C = 0),
+// so P(t + T e) = P(t) + pad_off(T e): one base register per thread and a
+// compile-time offset per element.
+template <class P, int T>
 __device__ __forceinline__ constexpr int lds_slot(int tpad, int e) {
-  static_assert(T % 16 == 0, "the pad split needs T to be a multiple of 16");
-  return tpad + T * e + ((T * e) >> 4);
+  static_assert(P::C == 0 || T % (1 << P::S) == 0, "the pad split needs T to be a multiple of 2^S");
+  return tpad + pad_off<P>(T * e);
 }
 
-// Padded LDS base of butterfly j's outputs in a Stockham pass of radix R and
-// span NS: position (j / NS) NS R + j mod NS (unsigned: shifts, no signed
+// Slot of butterfly j's first output in a Stockham pass of radix R and span
+// NS: position (j / NS) NS R + j mod NS (unsigned: shifts, no signed
 // division fix-up).
-template <int R, int NS>
+template <class P, int R, int NS>
 __device__ __forceinline__ int stockham_base(unsigned j) {
-  return lds_pad((int)((j / NS) * NS * R + (j & (NS - 1))));
+  return P::at((int)((j / NS) * NS * R + (j & (NS - 1))));
 }
 
-// True when, for every butterfly j, lds_pad(base_j + r NS) equals
-// lds_pad(base_j) + r NS + (r NS) / 16, i.e. the low four bits of base_j
-// plus those of r NS never carry: then the R scattered writes of a
-// butterfly use one address register and compile-time offsets.
-template <int R, int NS>
+// True when, for every butterfly j of an N-point pass, P(base_j + r NS) =
+// P(base_j) + pad_off(r NS): then the R scattered writes of a butterfly use
+// one address register and compile-time offsets.
+template <class P, int N, int R, int NS>
 constexpr bool pad_splits() {
-  for (int j = 0; j < 4096; ++j) {
+  for (int j = 0; j < N / R; ++j) {
     const int base = (j / NS) * NS * R + (j % NS);
     for (int r = 0; r < R; ++r)
-      if (lds_pad(base + r * NS) != lds_pad(base) + r * NS + ((r * NS) >> 4)) return false;
+      if (P::at(base + r * NS) != P::at(base) + pad_off<P>(r * NS)) return false;
   }
   return true;
 }
@@ -179,10 +207,11 @@ struct Engine {
     constexpr int B = E / R;
     constexpr bool LAST = (PASS == G::S::P - 1);
     if constexpr (PASS > 0) {
+      typedef Pad<LOG2N, PASS - 1> In;
       Lds raw[E];
-      const int tp = lds_pad(t);
+      const int tp = In::at(t);
 #pragma unroll
-      for (int e = 0; e < E; ++e) raw[e] = lds[lds_slot<T>(tp, e)];
+      for (int e = 0; e < E; ++e) raw[e] = lds[lds_slot<In, T>(tp, e)];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         v[b] = M::from_lds(raw[b]);
@@ -201,15 +230,15 @@ struct Engine {
       for (int r = 0; r < R; ++r) v[b + B * r] = u[r];
     }
     if constexpr (!LAST) {
-      static_assert(pad_splits<R, NS>(), "padded offsets of a butterfly must not straddle a pad");
+      typedef Pad<LOG2N, PASS> Out;
+      static_assert(pad_splits<Out, G::N, R, NS>(), "padded offsets of a butterfly must not straddle a pad");
       __syncthreads();  // all reads of the previous contents are done
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        const int pbase = stockham_base<R, NS>((unsigned)t + T * b);
-        // lds_pad(base + r NS) = lds_pad(base) + r NS + (r NS) / 16 (see pad_splits)
+        const int pbase = stockham_base<Out, R, NS>((unsigned)t + T * b);
+        // Out(base + r NS) = Out(base) + pad_off(r NS) (see pad_splits)
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-          lds[pbase + r * NS + ((r * NS) >> 4)] = M::to_lds(v[b + B * r]);
+        for (int r = 0; r < R; ++r) lds[pbase + pad_off<Out>(r * NS)] = M::to_lds(v[b + B * r]);
       }
       __syncthreads();
     }
@@ -267,10 +296,11 @@ struct Engine {
     constexpr bool LAST = (PASS == G::S::P - 1);
     if constexpr (PASS > 0) {
       const Lds *rd = buf[(x - 1) & 1];
+      typedef Pad<LOG2N, PASS - 1> In;
       Lds raw[E];
-      const int tp = lds_pad(t);
+      const int tp = In::at(t);
 #pragma unroll
-      for (int e = 0; e < E; ++e) raw[e] = rd[lds_slot<T>(tp, e)];
+      for (int e = 0; e < E; ++e) raw[e] = rd[lds_slot<In, T>(tp, e)];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         v[b] = M::from_lds(raw[b]);
@@ -288,14 +318,14 @@ struct Engine {
       for (int r = 0; r < R; ++r) v[b + B * r] = u[r];
     }
     if constexpr (!LAST) {
-      static_assert(pad_splits<R, NS>(), "padded offsets of a butterfly must not straddle a pad");
+      typedef Pad<LOG2N, PASS> Out;
+      static_assert(pad_splits<Out, G::N, R, NS>(), "padded offsets of a butterfly must not straddle a pad");
       Lds *wr = buf[x & 1];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        const int pbase = stockham_base<R, NS>((unsigned)t + T * b);
+        const int pbase = stockham_base<Out, R, NS>((unsigned)t + T * b);
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-          wr[pbase + r * NS + ((r * NS) >> 4)] = M::to_lds(v[b + B * r]);
+        for (int r = 0; r < R; ++r) wr[pbase + pad_off<Out>(r * NS)] = M::to_lds(v[b + B * r]);
       }
       __syncthreads();
       ++x;
