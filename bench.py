@@ -232,12 +232,16 @@ def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30, inverse=False):
     return res
 
 
-def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False):
+def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False, streams=1):
     """Full 4096x4096 range-Doppler frame: fused range compression, LDS-tiled
     corner turn, fused azimuth compression (fused_ct: the corner turn folded
     into the range compression's store, no separate pass).  n_frames
     independent frame buffer sets rotate (4 x 256 MiB for FP16) and the K
-    frames of a replay are captured once in a HIP graph."""
+    frames of a replay are captured once in a HIP graph.  streams > 1: the
+    frames of a replay are dealt round-robin to that many streams (default
+    priority) forked and joined inside the graph, so independent frames run
+    concurrently (frame k's memory-bound corner turn beside frame k+1's
+    compressions); each frame's three steps stay in order on its stream."""
     import torch
     from paper_2605_28451_amd import api, scenes
     fmt = api.storage_format(mode)
@@ -269,10 +273,21 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False)
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         g = torch.cuda.CUDAGraph()
+        side = [torch.cuda.Stream() for _ in range(streams - 1)]
         with torch.cuda.stream(s):
             with torch.cuda.graph(g, stream=s):
-                for i in range(n_frames):
-                    frame(i)
+                if streams == 1:
+                    for i in range(n_frames):
+                        frame(i)
+                else:
+                    lanes = [s] + side
+                    for q in side:
+                        q.wait_stream(s)  # fork
+                    for i in range(n_frames):
+                        with torch.cuda.stream(lanes[i % streams]):
+                            frame(i)
+                    for q in side:
+                        s.wait_stream(q)  # join
         torch.cuda.current_stream().wait_stream(s)
         g.replay()
         torch.cuda.synchronize()
@@ -291,7 +306,7 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False)
            "hbm_gbs": bytes_frame / (ms * 1e-3) / 1e9, "bytes_per_frame": bytes_frame,
            "gflops": fft_flops(n, 4 * n) / (ms * 1e-3) / 1e9, "graph": graph,
            "frames_rotating": n_frames, "corner_turn": "fused into the range store" if fused_ct
-           else "separate LDS-tiled pass"}
+           else "separate LDS-tiled pass", "concurrent_streams": streams}
     torch.cuda.synchronize()
     res["_img"] = api.to_host(imgs[0], fmt)
     res["_scene"] = sc
@@ -581,9 +596,15 @@ def main():
                                          for k, v in r.items() if not k.startswith("_")}
         sar["fp16_fused_corner_turn"]["image_equals_separate_corner_turn"] = bool(
             np.array_equal(r["_img"], sar_fp16_img))
+        for nst in (2, 4):
+            log(f"SAR frame 4096x4096 mode=fp16, {nst} frames concurrently on {nst} streams (graph)")
+            r = bench_sar_frame("fp16", args.steps, args.warmup, streams=nst)
+            sar[f"fp16_{nst}_streams"] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                          for k, v in r.items() if not k.startswith("_")}
+            sar[f"fp16_{nst}_streams"]["image_equals_one_stream"] = bool(np.array_equal(r["_img"], sar_fp16_img))
         out["sar_frame_4096"] = sar
-        out["sar_frames_per_s_fp16"] = max(sar["fp16"]["frames_per_s"],
-                                           sar["fp16_fused_corner_turn"]["frames_per_s"])
+        out["sar_frames_per_s_fp16"] = max(sar[k]["frames_per_s"] for k in
+                                           ("fp16", "fp16_fused_corner_turn", "fp16_2_streams", "fp16_4_streams"))
         log("weighted SAR frames (Taylor nbar=5, -40 dB): image quality per mode")
         wq = {"taper": "Taylor, nbar = 5, -40 dB, range (1024) and azimuth (512) filters"}
         wpts = {m: weighted_frame_metrics(m, ("taylor", 5, 40.0))

@@ -27,6 +27,11 @@
  *     last failure on the calling thread.
  *   - Plans are immutable after creation and may be used concurrently from
  *     several streams; a plan's non-finite counter is shared by all of them.
+ *     Exception: a plan's phasor table and its entropy and autofocus
+ *     workspaces are written by the calls that use them (an azimuth
+ *     compression given a phase vector, sar_image_entropy,
+ *     sar_azimuth_image_entropy, sar_azimuth_phase_grad); such calls must
+ *     not overlap on one plan (give each stream its own plan for them).
  */
 #ifndef BFPFFT_H
 #define BFPFFT_H

@@ -80,3 +80,54 @@ def test_uneven_graph_replays_match_eager():
         assert torch.equal(out, eager), f"replay {k}"
         plan.execute(x, out=out)
         torch.cuda.synchronize()
+
+
+def test_concurrent_frames_on_two_streams_match_eager():
+    # independent frames dealt to two streams forked and joined inside one
+    # graph (the benchmark's concurrent frames); the plans are shared, which
+    # the compression calls without a phase vector allow
+    need_gpu()
+    announce("graph: two SAR frames on two streams")
+    mode, fmt, n = "fp16", "fp16", 1024
+    sc = scenes.sar_scene(seed=3, n=n, length=256, aperture=128, ranges=(300,), azimuths=(n // 2,))
+    echo0 = upload(scenes.quantize(sc.echo, fmt), fmt)
+    echoes = [echo0, torch.flip(echo0, dims=[0]).contiguous()]
+    rp = api.FFTPlan(n, n, mode)
+    ap = api.FFTPlan(n, n, mode)
+    Hr = api.filter_tensor(sc.range_replica, n, mode)
+    Ha = api.filter_tensor(sc.azimuth_replica, n, mode)
+    bufs = [[torch.empty_like(echo0) for _ in range(3)] for _ in range(2)]
+
+    def frame(i):
+        rc, rct, img = bufs[i]
+        rp.range_compress(echoes[i], Hr, out=rc)
+        api.corner_turn(rc, fmt, out=rct)
+        ap.azimuth_compress(rct, Ha, out=img)
+
+    for i in range(2):
+        frame(i)
+    torch.cuda.synchronize()
+    eager = [bufs[i][2].clone() for i in range(2)]
+    assert not torch.equal(eager[0], eager[1])
+    side = torch.cuda.Stream()
+
+    def both():
+        main = torch.cuda.current_stream()
+        side.wait_stream(main)
+        frame(0)
+        with torch.cuda.stream(side):
+            frame(1)
+        main.wait_stream(side)
+
+    g = _capture(both)
+    for k in range(3):
+        for b in bufs:
+            b[2].zero_()
+            b[0].zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(2):
+            assert torch.equal(bufs[i][2], eager[i]), f"replay {k} frame {i}"
+        frame(0)  # eager work between replays
+        torch.cuda.synchronize()
