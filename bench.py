@@ -167,8 +167,9 @@ def rotating_sets(make, n_sets):
     return [make(i) for i in range(n_sets)]
 
 
-def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30):
-    """Fused range compression in `mode`, rotating buffers totalling >= min_bytes."""
+def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30, adaptive=False):
+    """Fused range compression in `mode`, rotating buffers totalling >= min_bytes
+    (adaptive: the per-row adaptive block shift, with its exponent rows)."""
     import torch
     from paper_2605_28451_amd import api, scenes
     sc = scenes.range_scene(seed=2, n_pulses=rows, n=n)
@@ -181,8 +182,13 @@ def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30):
     plan = api.FFTPlan(n, rows, mode)
     H = api.filter_tensor(sc.replica, n, mode)
 
+    exps = [torch.empty(rows, dtype=torch.int32, device="cuda") for _ in range(n_sets)]
+
     def launch(i):
-        plan.range_compress(ins[i], H, out=outs[i])
+        if adaptive:
+            plan.range_compress_adaptive(ins[i], H, out=outs[i], row_exp=exps[i])
+        else:
+            plan.range_compress(ins[i], H, out=outs[i])
 
     ms, total = time_launches(launch, n_sets, steps, warmup)
     res = {
@@ -433,6 +439,32 @@ def cpu_baseline(sample_in, replica, n, sample_out):
     }, sq, sq_raw
 
 
+def adaptive_shift_quality(rows=256, scales=(0, -12, -16)):
+    """Pure FP16 compression of the range scene's echo scaled by 2^s, fixed
+    and adaptive block shift, each against the GPU FP32 path on the same
+    FP16-rounded echo (SQNR, dB)."""
+    from paper_2605_28451_amd import api, scenes
+    from paper_2605_28451_amd.metrics import sqnr_db
+    sc = scenes.range_scene(seed=2, n_pulses=rows)
+    p16 = api.FFTPlan(4096, rows, "fp16")
+    p32 = api.FFTPlan(4096, rows, "fp32")
+    H16 = api.filter_tensor(sc.replica, 4096, "fp16")
+    H32 = api.filter_tensor(sc.replica, 4096, "fp32")
+    out = {}
+    for ls in scales:
+        e16 = scenes.quantize(sc.echo * 2.0 ** ls, "fp16")
+        ref = api.to_host(p32.range_compress(api.to_device(e16, "fp32"), H32), "fp32")
+        d16 = api.to_device(e16, "fp16")
+        fixed = api.to_host(p16.range_compress(d16, H16), "fp16")
+        y, ex = p16.range_compress_adaptive(d16, H16)
+        ad = api.to_host(y, "fp16") * np.ldexp(1.0, ex.cpu().numpy().astype(np.int64))[:, None]
+        out[f"scale_2^{ls}"] = {"fixed_sqnr_db": round(sqnr_db(ref, fixed), 2),
+                                "adaptive_sqnr_db": round(sqnr_db(ref, ad), 2)}
+    p16.close()
+    p32.close()
+    return out
+
+
 def weighted_frame_metrics(mode, taper):
     """Point-target metrics of one 4096x4096 frame whose range and azimuth
     matched filters are weighted (taper: ("taylor", nbar, sll_db) or
@@ -617,6 +649,13 @@ def main():
                      "islr_range_db_mean": round(float(np.mean([p["islr_range"] for p in pts])), 3),
                      "max_pslr_shift_vs_fp32_path_db": round(float(shift), 3)}
         out["sar_frame_4096_weighted"] = wq
+        log("adaptive block shift: fused compression 2048x4096 fp16, time and quality")
+        r = bench_compress("fp16", 2048, 4096, args.steps, args.warmup, adaptive=True)
+        out["range_compress_adaptive_shift"] = {
+            "ms_per_launch": round(r["ms_per_launch"], 5),
+            "ms_per_launch_fixed_shift": round(head["ms_per_launch"], 5),
+            "hbm_gbs": round(r["hbm_gbs"], 1),
+            "sqnr_vs_fp32_path_by_echo_scale": adaptive_shift_quality()}
         log("uneven batch 20000 transforms fp16")
         ub = bench_uneven("fp16", args.steps, args.warmup)
         out["uneven_20000"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in ub.items()}

@@ -215,6 +215,27 @@ int bfp_window(int kind, int len, int nbar, double sll_db, double *out_host);
 int bfp_convert(const void *in, int in_fmt, void *out, int out_fmt, long long count,
                 void *stream);
 
+/* Adaptive block shift (the per-block exponents the paper leaves as future
+ * work, Sec. VIII).  The fixed shift 2^-log2N of Eq. (1) keeps the inverse
+ * in range for every input but pushes weak rows toward the FP16
+ * subnormals.  These variants choose the shift per row: with z the
+ * inverse's input (after the filter product) and M the largest |Re z| or
+ * |Im z| of the row, k is the smallest integer in [-15, 14] with
+ * sqrt(2) N M 2^-k < 2^15 (-15 for an all-zero row), which bounds every
+ * partial sum of the inverse by 2^15 and scales weak rows up.  Each output row holds the normalised result times 2^(log2N - k);
+ * (device) row_exp[r] = k - log2N, so the true row is out[r] * 2^row_exp[r].
+ * FP16-storage modes only (BFP_FP16, BFP_FP16_STORE_FP32_COMPUTE,
+ * BFP_FP16_MUL_FP32_ACC; else BFP_EUNSUPPORTED); flags: BFP_FLAG_CHECK_FINITE
+ * only, and the plan may not carry NAIVE_POSTSCALE, CONJ_FILTER or OUT_FP32.
+ * row_exp holds the plan's batch (inverse) or n_pulses (compression) ints.
+ * Each row's maximum is a workgroup reduction (one LDS atomic per thread
+ * and one barrier per row). */
+int fft_exec_inv_bfp_adaptive(bfp_plan p, const void *in, void *out, const void *filter,
+                              int *row_exp, unsigned flags, void *stream);
+int sar_range_compress_adaptive(bfp_plan range_plan, const void *echo, void *rc,
+                                const void *h_range, int n_pulses, int *row_exp, unsigned flags,
+                                void *stream);
+
 /* Plain streaming copy of `bytes` (multiple of 16; 16-byte aligned
  * pointers), 16 bytes per lane: the reference for achievable HBM bandwidth
  * and for calibrating hardware memory counters against known traffic. */

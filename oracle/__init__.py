@@ -167,3 +167,23 @@ def autofocus(rc_t, Ha, phi, want_image: bool = False):
     img = np.empty_like(rc_t) if want_image else None
     E = _load().oracle_autofocus(_ptr(rc_t), nr, npul, _ptr(Ha), _ptr(ph), _ptr(g), _ptr(img))
     return (E, g, img) if want_image else (E, g)
+
+
+def adaptive_exponent(z, n: int):
+    """Per-row exponent of the adaptive block shift (the per-block exponents
+    of Sec. VIII's future work, as this library defines them): for the
+    inverse's input row z (after the filter product) with M = max(|Re z|,
+    |Im z|), k is the smallest integer in [-15, 14] with
+    sqrt(2) n M 2^-k < 2^15; returns k - log2(n) per row (true output =
+    stored output * 2^exponent).  Plain loops, FP64."""
+    z = np.atleast_2d(_c128(z))
+    log2n = int(n).bit_length() - 1
+    out = np.empty(z.shape[0], dtype=np.int64)
+    for r in range(z.shape[0]):
+        m = max(np.max(np.abs(z[r].real)), np.max(np.abs(z[r].imag)))
+        b = np.sqrt(2.0) * n * m
+        k = -15
+        while k < 14 and b * 2.0 ** -k >= 2.0 ** 15:
+            k += 1
+        out[r] = k - log2n
+    return out

@@ -63,6 +63,8 @@ SIGNATURES = {
     "fft_exec_uneven": (_I, [_P, _P, _P, _P]),
     "bfp_make_filter": (_I, [_P, _I, _I, _I, _P]),
     "bfp_window": (_I, [_I, _I, _I, ctypes.c_double, _P]),
+    "fft_exec_inv_bfp_adaptive": (_I, [_P, _P, _P, _P, _P, ctypes.c_uint, _P]),
+    "sar_range_compress_adaptive": (_I, [_P, _P, _P, _P, _I, _P, ctypes.c_uint, _P]),
     "bfp_convert": (_I, [_P, _I, _P, _I, _LL, _P]),
     "bfp_device_copy": (_I, [_P, _P, _LL, _P]),
     "sar_range_compress": (_I, [_P, _P, _P, _P, _I, _U, _P]),

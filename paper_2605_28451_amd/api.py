@@ -169,6 +169,34 @@ class FFTPlan:
                                                  _stream(stream)), "fft_exec_inv_bfp")
         return out
 
+    def inverse_bfp_adaptive(self, z, filt=None, out=None, row_exp=None, stream=None):
+        """BFP inverse with a per-row adaptive shift: returns (out, row_exp);
+        the true rows are out[r] * 2**row_exp[r] (int32 row_exp on the device)."""
+        self._rows_of(z, None)
+        out = self._out(out, self.batch, False)
+        if filt is not None:
+            _check_storage(filt, self.filter_fmt, self.n, "filter")
+        if row_exp is None:
+            row_exp = torch.empty(self.batch, dtype=torch.int32, device=out.device)
+        assert row_exp.dtype == torch.int32 and row_exp.numel() >= self.batch and row_exp.is_contiguous()
+        check(_lib.load().fft_exec_inv_bfp_adaptive(self._h, _ptr(z), _ptr(out), _ptr(filt),
+                                                    _ptr(row_exp), 0, _stream(stream)),
+              "fft_exec_inv_bfp_adaptive")
+        return out, row_exp
+
+    def range_compress_adaptive(self, echo, filt, out=None, rows=None, row_exp=None, stream=None):
+        """Fused compression with a per-row adaptive shift: (out, row_exp)."""
+        rows = self._rows_of(echo, rows)
+        out = self._out(out, rows, False)
+        _check_storage(filt, self.filter_fmt, self.n, "filter")
+        if row_exp is None:
+            row_exp = torch.empty(rows, dtype=torch.int32, device=out.device)
+        assert row_exp.dtype == torch.int32 and row_exp.numel() >= rows and row_exp.is_contiguous()
+        check(_lib.load().sar_range_compress_adaptive(self._h, _ptr(echo), _ptr(out), _ptr(filt),
+                                                      rows, _ptr(row_exp), 0, _stream(stream)),
+              "sar_range_compress_adaptive")
+        return out, row_exp
+
     def range_compress(self, echo, filt, out=None, rows=None, naive=False, out_fp32=False,
                        transposed=False, stream=None):
         """transposed=True stores the result corner-turned, shape (n, rows):

@@ -158,7 +158,7 @@ unsigned kflags(unsigned f) {
 
 int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
              const void *phasor, int rows, unsigned flags, void *stream,
-             double *ent_partial = nullptr, int *grid_used = nullptr) {
+             double *ent_partial = nullptr, int *grid_used = nullptr, int *row_exp = nullptr) {
   if (rows < 0 || rows > p->batch) return fail(BFP_EINVAL, "row count outside [0, plan batch]");
   if (rows == 0) return BFP_OK;
   if (!in || !out) return fail(BFP_EINVAL, "NULL data pointer");
@@ -177,6 +177,8 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   a.grid_limit = bpc > 0 ? bpc * p->cu_count : 0;
   a.engine = p->tune_engine;
   a.ent_partial = ent_partial;
+  a.row_exp = row_exp;
+  if (row_exp) a.flags |= bfp::KF_ADAPT;
   if (grid_used) *grid_used = bfp::rows_grid(p->log2n, rows, a.grid_limit);
   const bool out32 = ((flags | p->flags) & BFP_FLAG_OUT_FP32) != 0;
   int cur = 0;
@@ -345,6 +347,30 @@ int fft_exec_inv_bfp(bfp_plan p, const void *in, void *out, const void *filter, 
   return fft_exec_inv_bfp_flags(p, in, out, filter, 0u, stream);
 }
 
+namespace {
+// the adaptive shift exists for the modes with FP16 storage between passes
+int check_adaptive(bfp_plan p, const int *row_exp) {
+  if (!row_exp) return fail(BFP_EINVAL, "row_exp is NULL");
+  if (p->prec != BFP_FP16 && p->prec != BFP_FP16_STORE_FP32_COMPUTE && p->prec != BFP_FP16_MUL_FP32_ACC)
+    return fail(BFP_EUNSUPPORTED, "the adaptive shift is for the FP16-storage modes");
+  if (p->flags & (BFP_FLAG_NAIVE_POSTSCALE | BFP_FLAG_CONJ_FILTER | BFP_FLAG_OUT_FP32))
+    return fail(BFP_EUNSUPPORTED, "the adaptive shift combines with BFP_FLAG_CHECK_FINITE only");
+  return BFP_OK;
+}
+}  // namespace
+
+int fft_exec_inv_bfp_adaptive(bfp_plan p, const void *in, void *out, const void *filter,
+                              int *row_exp, unsigned flags, void *stream) {
+  int st = check_rows_plan(p);
+  if (st) return st;
+  if (flags & ~(unsigned)BFP_FLAG_CHECK_FINITE)
+    return fail(BFP_EINVAL, "the adaptive inverse takes BFP_FLAG_CHECK_FINITE only");
+  st = check_adaptive(p, row_exp);
+  if (st) return st;
+  return run_rows(p, bfp::OP_INV, in, out, filter, nullptr, p->batch, flags, stream, nullptr,
+                  nullptr, row_exp);
+}
+
 int fft_plan_nonfinite(bfp_plan p, void *stream, unsigned long long *count) {
   if (!p || !count) return fail(BFP_EINVAL, "NULL argument");
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
@@ -408,6 +434,21 @@ int sar_range_compress(bfp_plan range_plan, const void *echo, void *rc, const vo
   if (echo == rc) return fail(BFP_EINVAL, "echo and rc must differ");
   return run_rows(range_plan, bfp::OP_COMPRESS, echo, rc, h_range, nullptr, n_pulses, flags,
                   stream);
+}
+
+int sar_range_compress_adaptive(bfp_plan range_plan, const void *echo, void *rc,
+                                const void *h_range, int n_pulses, int *row_exp, unsigned flags,
+                                void *stream) {
+  int st = check_rows_plan(range_plan);
+  if (st) return st;
+  if (!h_range) return fail(BFP_EINVAL, "range filter is NULL");
+  if (flags & ~(unsigned)BFP_FLAG_CHECK_FINITE)
+    return fail(BFP_EINVAL, "the adaptive compression takes BFP_FLAG_CHECK_FINITE only");
+  st = check_adaptive(range_plan, row_exp);
+  if (st) return st;
+  if (echo == rc) return fail(BFP_EINVAL, "echo and rc must differ");
+  return run_rows(range_plan, bfp::OP_COMPRESS, echo, rc, h_range, nullptr, n_pulses, flags,
+                  stream, nullptr, nullptr, row_exp);
 }
 
 int bfp_device_copy(const void *in, void *out, long long bytes, void *stream) {

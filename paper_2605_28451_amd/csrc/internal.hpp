@@ -16,6 +16,7 @@ enum KFlags : unsigned {
   KF_CHECK_FINITE = 2u,  // count non-finite outputs
   KF_TRANSPOSED = 4u,    // compression: store out[k][row] (n x rows)
   KF_CONJ_FILTER = 16u,  // multiply by conj(filter)
+  KF_ADAPT = 32u,        // per-row adaptive block shift (row_exp)
 };
 
 struct RowArgs {
@@ -31,6 +32,7 @@ struct RowArgs {
   int engine;            // 0: matrix cores where available, 1: vector ALU only
   double *ent_partial;   // compression to FP32 with phasor: per-workgroup (S, Q) of the
                          // output's entropy sums (see rows_grid), or NULL
+  int *row_exp;          // KF_ADAPT: per-row block exponent of the output, or NULL
 };
 
 // Workgroups a row launch uses (what the per-workgroup partials count).

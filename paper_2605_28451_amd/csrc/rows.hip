@@ -46,7 +46,35 @@ __device__ __forceinline__ h2 mul_c32(h2 v, c32 p) { return cmul(v, c32_to_h2(p)
 // Compile-time variants of the inverse / compression kernels (no runtime
 // selects in the per-element code): conventional post-scaling (debug),
 // conjugated filter (adjoint), per-pulse phasor at load.
-enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4, V_TRANS = 8, V_ENT = 16 };
+enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4, V_TRANS = 8, V_ENT = 16,
+               V_ADAPT = 32 };
+
+// Adaptive block shift of one transform (the per-block exponents the paper
+// leaves as future work, Sec. VIII): with M the largest |Re| or |Im| of the
+// inverse's input z (after the filter product), every partial sum of the
+// inverse is bounded by sqrt(2) N M 2^-k after a shift 2^-k, so the
+// smallest k with sqrt(2) N M 2^-k < 2^15 keeps all of them below 2^15 (half
+// the FP16 range) while scaling weak rows up instead of pushing them toward
+// the FP16 subnormals as the fixed k = log2 N does.  With sqrt(2) N M =
+// f 2^x, 1/2 <= f < 1: k = x - 15, kept in [-15, 14] (2^15 and 2^-14 are
+// normal FP16 numbers; k = -15 for an all-zero row).  The stored output is the normalised inverse times 2^(log2N - k);
+// the kernel writes row_exp = k - log2 N, so true value = stored 2^row_exp.
+template <int LOG2N>
+__device__ __forceinline__ int adaptive_shift(float m) {
+  int x = 0;
+  (void)frexpf(1.41421356f * (float)(1 << LOG2N) * m, &x);
+  const int k = x - 15;
+  return k < -15 ? -15 : (k > 14 ? 14 : k);
+}
+__device__ __forceinline__ float max_component(c32 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
+__device__ __forceinline__ float max_component(h2 v) {
+  return fmaxf(fabsf((float)v.x), fabsf((float)v.y));
+}
+// conj(v) . 2^-k for a run-time k (exact: a power of two, never contracted)
+__device__ __forceinline__ c32 conj_scale(c32 v, float s) { return c32{v.x * s, -(v.y * s)}; }
+__device__ __forceinline__ h2 conj_scale(h2 v, float s) {
+  return pk_scale(v, h2{(f16)s, (f16)(-s)});
+}
 
 // Order of the row groups of a transposed store.  Workgroups are dispatched
 // to the 8 XCDs in turn (workgroup w on XCD w mod 8), so the groups of
@@ -84,6 +112,11 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   static_assert(!ent || (OP == OP_COMPRESS && (V & ~V_PHASOR) == V_ENT && OUT32),
                 "entropy sums are a variant of the (phase-corrected) compression to FP32");
   double es = 0.0, eq = 0.0;
+  // adaptive block shift (V_ADAPT): per-transform max through LDS
+  constexpr bool adapt = (V & V_ADAPT) != 0;
+  static_assert(!adapt || ((OP == OP_INV || OP == OP_COMPRESS) && V == V_ADAPT && !OUT32),
+                "the adaptive shift is a variant of the plain inverse and compression");
+  __shared__ unsigned amax[adapt ? G::TPW : 1];
 
   // the pipelined kernel alternates two LDS buffers (one barrier per exchange)
   __shared__ typename M::Lds lds_all[(PIPE ? 2 : 1) * G::TPW * G::LDS_N];
@@ -143,6 +176,13 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   // empty statement emits no instruction)
   unsigned tt = t;
   asm volatile("" : "+v"(tt));
+  if constexpr (adapt) {
+    // the previous row read amax before its inverse transform, whose
+    // barriers every thread has passed; the forward transform's barriers
+    // (compression) or this one (inverse) order the reset before the maxima
+    if (tt == 0) amax[local] = 0u;
+    if constexpr (OP == OP_INV) __syncthreads();
+  }
   if constexpr (PIPE) {
     // likewise the register twiddles and filter: hoisted, each FP16 pair
     // would be kept twice, pre-broadcast as (re, re) and (im, im), instead
@@ -205,7 +245,29 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
     constexpr int K = naive ? 0 : LOG2N;  // block shift 2^-log2N
     // compression always carries a filter (checked by the C layer), so its
     // kernels have no run-time branch here
-    if (OP == OP_COMPRESS || f) {
+    if constexpr (adapt) {
+      if (OP == OP_COMPRESS || f) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          Filt h;
+          if constexpr (kHoist) h = hf[e];
+          else h = f[tt + T * e];
+          v[e] = M::fmul(v[e], h);
+        }
+      }
+      // the largest component of the transform's z (non-negative floats
+      // order like their bit patterns)
+      float m = 0.0f;
+#pragma unroll
+      for (int e = 0; e < E; ++e) m = fmaxf(m, max_component(v[e]));
+      atomicMax(&amax[local], __float_as_uint(m));
+      __syncthreads();
+      const int k = adaptive_shift<LOG2N>(__uint_as_float(amax[local]));
+      if (active && tt == 0) a.row_exp[row] = k - LOG2N;
+      const float sc = __uint_as_float((unsigned)(127 - k) << 23);  // 2^-k
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = conj_scale(v[e], sc);
+    } else if (OP == OP_COMPRESS || f) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         Filt h;
@@ -418,7 +480,7 @@ static hipError_t launch_one(const RowArgs &a, hipStream_t s) {
   typedef Geometry<LOG2N> G;
   if (a.rows <= 0) return hipSuccess;
 #if BFP_MODE_ID == 3
-  if constexpr (LOG2N == 12 && (V & V_TRANS) == 0) {
+  if constexpr (LOG2N == 12 && (V & (V_TRANS | V_ADAPT)) == 0) {
     if (a.engine == 0) return launch_mfma<OP, V, OUT32>(a, s);
   }
 #endif
@@ -446,11 +508,28 @@ static hipError_t launch_size(int op, bool out32, const RowArgs &a, hipStream_t 
       return out32 ? launch_one<LOG2N, OP_FWD, V_PLAIN, true>(a, s)
                    : launch_one<LOG2N, OP_FWD, V_PLAIN, false>(a, s);
     case OP_INV:
+      if (a.flags & KF_ADAPT) {
+        if (out32 || ph || naive || conj || !a.row_exp) return hipErrorInvalidValue;
+#if BFP_MODE_ID >= 1 && BFP_MODE_ID <= 3
+        return launch_one<LOG2N, OP_INV, V_ADAPT, false>(a, s);
+#else
+        return hipErrorInvalidValue;
+#endif
+      }
       if (out32 || ph || (naive && conj)) return hipErrorInvalidValue;
       if (naive) return launch_one<LOG2N, OP_INV, V_NAIVE, false>(a, s);
       if (conj) return launch_one<LOG2N, OP_INV, V_CONJ, false>(a, s);
       return launch_one<LOG2N, OP_INV, V_PLAIN, false>(a, s);
     case OP_COMPRESS:
+      if (a.flags & KF_ADAPT) {
+        if (out32 || ph || naive || conj || a.ent_partial || (a.flags & KF_TRANSPOSED) || !a.row_exp)
+          return hipErrorInvalidValue;
+#if BFP_MODE_ID >= 1 && BFP_MODE_ID <= 3
+        return launch_one<LOG2N, OP_COMPRESS, V_ADAPT, false>(a, s);
+#else
+        return hipErrorInvalidValue;
+#endif
+      }
       if (a.flags & KF_TRANSPOSED) {
         if (naive || conj || ph || out32) return hipErrorInvalidValue;
         return launch_one<LOG2N, OP_COMPRESS, V_TRANS, false>(a, s);

@@ -294,3 +294,30 @@ def test_weighted_point_target_sidelobes_and_broadening():
     assert abs(res["taylor"][0] + 40.0) <= 0.7
     assert abs(res["hamming"][2] / res["rect"][2] - 1.47) <= 0.03
     assert res["rect"][2] < res["taylor"][2] < res["hamming"][2]
+
+
+def test_adaptive_exponent_rule():
+    # smallest k in [-15, 14] with sqrt(2) n M 2^-k < 2^15, as k - log2 n
+    n = 4096
+    at = lambda m: int(oracle.adaptive_exponent(np.array([[m + 0j]]), n)[0]) + 12
+    assert at(0.0) == -15                                # an all-zero row: the floor
+    edge = 2.0 ** 15 / (np.sqrt(2.0) * n)                # sqrt(2) n M = 2^15 exactly
+    assert at(edge * (1 - 1e-12)) == 0 and at(edge) == 1
+    assert at(edge * 2 * (1 - 1e-12)) == 1 and at(edge * 2) == 2
+    assert at(edge / 8) == -2 and at(edge / 8 * (1 - 1e-12)) == -3
+    assert at(1.0) == -2                                 # sqrt(2) 4096 = 2^12.5: 2^14.5 < 2^15
+    assert at(64.0) == 4                                 # 2^18.5: 2^14.5 < 2^15 <= 2^15.5
+    assert at(1e-30) == -15
+    assert at(1e30) == 14                                # capped
+    # the component maximum, not the modulus, and per row
+    z = np.array([[3.0 + 4.0j, -5.0 + 0j], [0.0 + 0.0j, 0.0 + 0.0j]])
+    e = oracle.adaptive_exponent(z, n)
+    assert e[1] == -15 - 12 and e[0] == oracle.adaptive_exponent(np.array([[5.0 + 0j]]), n)[0]
+    # bound and minimality on random rows
+    rng = np.random.default_rng(9)
+    rows = (rng.standard_normal((50, n)) + 1j * rng.standard_normal((50, n))) * 10.0 ** rng.uniform(-6, 2, (50, 1))
+    for row, ex in zip(rows, oracle.adaptive_exponent(rows, n)):
+        k = ex + 12
+        b = np.sqrt(2.0) * n * max(np.abs(row.real).max(), np.abs(row.imag).max())
+        assert -15 <= k <= 14 and b * 2.0 ** -k < 2.0 ** 15
+        assert k == -15 or b * 2.0 ** -(k - 1) >= 2.0 ** 15
