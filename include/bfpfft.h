@@ -236,6 +236,20 @@ int sar_range_compress_adaptive(bfp_plan range_plan, const void *echo, void *rc,
                                 const void *h_range, int n_pulses, int *row_exp, unsigned flags,
                                 void *stream);
 
+/* Range compression with range cell migration correction (the RCMC step of
+ * the range-Doppler pipeline, Sec. VI), for data already in the Doppler
+ * domain: row r of in (n_rows x n, one Doppler bin per row) becomes
+ *   IDFT( DFT(in_r) . H . exp(+2 pi i k' s_r / n) ),  k' = k or k - n (k >= n/2),
+ * with the BFP fold of Eq. (1): the row compressed by H and moved s_r bins
+ * toward smaller range by band-limited (periodic sinc) interpolation.
+ * (device) shift[n_rows]: s_r in range bins (FP32, any real value).  All
+ * precision modes; flags: BFP_FLAG_CHECK_FINITE only; in != out.  The
+ * linear phase is evaluated per element in FP32 (sincospif of the phase
+ * reduced to [-1/2, 1/2] cycles) and multiplied into H before the filter
+ * product. */
+int sar_range_compress_rcmc(bfp_plan range_plan, const void *in, void *out, const void *h_range,
+                            const float *shift, int n_rows, unsigned flags, void *stream);
+
 /* Plain streaming copy of `bytes` (multiple of 16; 16-byte aligned
  * pointers), 16 bytes per lane: the reference for achievable HBM bandwidth
  * and for calibrating hardware memory counters against known traffic. */

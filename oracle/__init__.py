@@ -187,3 +187,32 @@ def adaptive_exponent(z, n: int):
             k += 1
         out[r] = k - log2n
     return out
+
+
+def rcmc_compress(x, H, shift):
+    """Range compression with range cell migration correction, row by row:
+    y_r = IDFT(DFT(x_r) . H . exp(+2 pi i k s_r / n)), k the signed bin
+    (k - n for k >= n/2).  The linear phase is the band-limited (periodic
+    sinc) interpolation y_r[t] = (x_r compressed)[t + s_r]: it moves the row
+    s_r bins toward smaller range."""
+    x = _c128(x)
+    n = x.shape[-1]
+    shift = np.asarray(shift, dtype=np.float64).reshape(-1)
+    assert shift.size == x.shape[0]
+    k = np.arange(n, dtype=np.float64)
+    k[n // 2:] -= n
+    X = fft(x)
+    ramp = np.exp(2j * np.pi * k[None, :] * shift[:, None] / n)
+    return fft(X * _c128(H).reshape(1, -1) * ramp, inverse=True)
+
+
+def rda_rcmc_image(echo, Hr, Ha, shift):
+    """Range-Doppler image [range][azimuth] of an echo [pulse][range] with
+    range cell migration correction: azimuth DFT (pulses -> Doppler), per
+    Doppler bin the range compression with that bin's migration shift
+    (rcmc_compress), then per range bin the azimuth compression in the
+    Doppler domain, IDFT(. Ha)."""
+    echo = _c128(echo)
+    rd = transpose(fft(transpose(echo)))          # [Doppler][range]
+    rc = rcmc_compress(rd, Hr, shift)             # migration removed
+    return fft(transpose(rc) * _c128(Ha).reshape(1, -1), inverse=True)

@@ -65,6 +65,7 @@ SIGNATURES = {
     "bfp_window": (_I, [_I, _I, _I, ctypes.c_double, _P]),
     "fft_exec_inv_bfp_adaptive": (_I, [_P, _P, _P, _P, _P, ctypes.c_uint, _P]),
     "sar_range_compress_adaptive": (_I, [_P, _P, _P, _P, _I, _P, ctypes.c_uint, _P]),
+    "sar_range_compress_rcmc": (_I, [_P, _P, _P, _P, _P, _I, ctypes.c_uint, _P]),
     "bfp_convert": (_I, [_P, _I, _P, _I, _LL, _P]),
     "bfp_device_copy": (_I, [_P, _P, _LL, _P]),
     "sar_range_compress": (_I, [_P, _P, _P, _P, _I, _U, _P]),

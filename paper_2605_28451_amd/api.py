@@ -197,6 +197,19 @@ class FFTPlan:
               "sar_range_compress_adaptive")
         return out, row_exp
 
+    def range_compress_rcmc(self, x, filt, shift, out=None, rows=None, stream=None):
+        """Range compression with migration correction of Doppler-domain rows:
+        row r compressed by filt and moved shift[r] bins toward smaller range
+        (shift: device float32, one per row)."""
+        rows = self._rows_of(x, rows)
+        out = self._out(out, rows, False)
+        _check_storage(filt, self.filter_fmt, self.n, "filter")
+        assert shift.dtype == torch.float32 and shift.numel() >= rows and shift.is_contiguous()
+        check(_lib.load().sar_range_compress_rcmc(self._h, _ptr(x), _ptr(out), _ptr(filt),
+                                                  _ptr(shift), rows, 0, _stream(stream)),
+              "sar_range_compress_rcmc")
+        return out
+
     def range_compress(self, echo, filt, out=None, rows=None, naive=False, out_fp32=False,
                        transposed=False, stream=None):
         """transposed=True stores the result corner-turned, shape (n, rows):

@@ -158,7 +158,8 @@ unsigned kflags(unsigned f) {
 
 int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
              const void *phasor, int rows, unsigned flags, void *stream,
-             double *ent_partial = nullptr, int *grid_used = nullptr, int *row_exp = nullptr) {
+             double *ent_partial = nullptr, int *grid_used = nullptr, int *row_exp = nullptr,
+             const float *shift = nullptr) {
   if (rows < 0 || rows > p->batch) return fail(BFP_EINVAL, "row count outside [0, plan batch]");
   if (rows == 0) return BFP_OK;
   if (!in || !out) return fail(BFP_EINVAL, "NULL data pointer");
@@ -179,6 +180,8 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   a.ent_partial = ent_partial;
   a.row_exp = row_exp;
   if (row_exp) a.flags |= bfp::KF_ADAPT;
+  a.shift = shift;
+  if (shift) a.flags |= bfp::KF_RAMP;
   if (grid_used) *grid_used = bfp::rows_grid(p->log2n, rows, a.grid_limit);
   const bool out32 = ((flags | p->flags) & BFP_FLAG_OUT_FP32) != 0;
   int cur = 0;
@@ -449,6 +452,21 @@ int sar_range_compress_adaptive(bfp_plan range_plan, const void *echo, void *rc,
   if (echo == rc) return fail(BFP_EINVAL, "echo and rc must differ");
   return run_rows(range_plan, bfp::OP_COMPRESS, echo, rc, h_range, nullptr, n_pulses, flags,
                   stream, nullptr, nullptr, row_exp);
+}
+
+int sar_range_compress_rcmc(bfp_plan range_plan, const void *in, void *out, const void *h_range,
+                            const float *shift, int n_rows, unsigned flags, void *stream) {
+  int st = check_rows_plan(range_plan);
+  if (st) return st;
+  if (!h_range) return fail(BFP_EINVAL, "range filter is NULL");
+  if (!shift) return fail(BFP_EINVAL, "shift is NULL");
+  if (flags & ~(unsigned)BFP_FLAG_CHECK_FINITE)
+    return fail(BFP_EINVAL, "the migration-corrected compression takes BFP_FLAG_CHECK_FINITE only");
+  if (range_plan->flags & (BFP_FLAG_NAIVE_POSTSCALE | BFP_FLAG_CONJ_FILTER | BFP_FLAG_OUT_FP32))
+    return fail(BFP_EUNSUPPORTED, "the migration-corrected compression combines with BFP_FLAG_CHECK_FINITE only");
+  if (in == out) return fail(BFP_EINVAL, "in and out must differ");
+  return run_rows(range_plan, bfp::OP_COMPRESS, in, out, h_range, nullptr, n_rows, flags, stream,
+                  nullptr, nullptr, nullptr, shift);
 }
 
 int bfp_device_copy(const void *in, void *out, long long bytes, void *stream) {

@@ -17,6 +17,7 @@ enum KFlags : unsigned {
   KF_TRANSPOSED = 4u,    // compression: store out[k][row] (n x rows)
   KF_CONJ_FILTER = 16u,  // multiply by conj(filter)
   KF_ADAPT = 32u,        // per-row adaptive block shift (row_exp)
+  KF_RAMP = 64u,         // compression: per-row range shift (shift)
 };
 
 struct RowArgs {
@@ -33,6 +34,7 @@ struct RowArgs {
   double *ent_partial;   // compression to FP32 with phasor: per-workgroup (S, Q) of the
                          // output's entropy sums (see rows_grid), or NULL
   int *row_exp;          // KF_ADAPT: per-row block exponent of the output, or NULL
+  const float *shift;    // KF_RAMP: per-row range shift in bins (RCMC), or NULL
 };
 
 // Workgroups a row launch uses (what the per-workgroup partials count).

@@ -47,7 +47,28 @@ __device__ __forceinline__ h2 mul_c32(h2 v, c32 p) { return cmul(v, c32_to_h2(p)
 // selects in the per-element code): conventional post-scaling (debug),
 // conjugated filter (adjoint), per-pulse phasor at load.
 enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4, V_TRANS = 8, V_ENT = 16,
-               V_ADAPT = 32 };
+               V_ADAPT = 32, V_RAMP = 64 };
+
+// Range cell migration correction folded into the range compression (the
+// RCMC step of the range-Doppler pipeline, Sec. VI): row r (one Doppler
+// bin) multiplies its spectrum by H[k] exp(+2 pi i k' s_r / N), k' the
+// signed bin (k - N for k >= N/2), which is the band-limited (periodic sinc)
+// interpolation moving the compressed row s_r bins toward smaller range.
+// The phase is reduced to [-1/2, 1/2] cycles in FP32 and evaluated by
+// sincospif; the product with H is formed in FP32 and rounded once to the
+// filter type.
+template <int LOG2N>
+__device__ __forceinline__ c32 rcmc_ramp(unsigned k, float s) {
+  constexpr int N = 1 << LOG2N;
+  const float kk = (float)((int)k - (k >= (unsigned)(N / 2) ? N : 0));
+  float cyc = kk * s * (1.0f / N);
+  cyc -= rintf(cyc);
+  float sn, cs;
+  sincospif(2.0f * cyc, &sn, &cs);
+  return c32{cs, sn};
+}
+__device__ __forceinline__ void filt_from_c32(c32 v, c32 &h) { h = v; }
+__device__ __forceinline__ void filt_from_c32(c32 v, h2 &h) { h = c32_to_h2(v); }
 
 // Adaptive block shift of one transform (the per-block exponents the paper
 // leaves as future work, Sec. VIII): with M the largest |Re| or |Im| of the
@@ -117,6 +138,9 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   static_assert(!adapt || ((OP == OP_INV || OP == OP_COMPRESS) && V == V_ADAPT && !OUT32),
                 "the adaptive shift is a variant of the plain inverse and compression");
   __shared__ unsigned amax[adapt ? G::TPW : 1];
+  constexpr bool ramp = (V & V_RAMP) != 0;
+  static_assert(!ramp || (OP == OP_COMPRESS && V == V_RAMP && !OUT32),
+                "the migration ramp is a variant of the plain compression");
 
   // the pipelined kernel alternates two LDS buffers (one barrier per exchange)
   __shared__ typename M::Lds lds_all[(PIPE ? 2 : 1) * G::TPW * G::LDS_N];
@@ -267,6 +291,16 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
       const float sc = __uint_as_float((unsigned)(127 - k) << 23);  // 2^-k
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = conj_scale(v[e], sc);
+    } else if constexpr (ramp) {
+      const float sr = active ? a.shift[row] : 0.0f;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        Filt h;
+        if constexpr (kHoist) h = hf[e];
+        else h = f[tt + T * e];
+        filt_from_c32(cmul(to_c32(h), rcmc_ramp<LOG2N>(tt + T * e, sr)), h);
+        v[e] = conj_pow2<K>(M::fmul(v[e], h));
+      }
     } else if (OP == OP_COMPRESS || f) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -480,7 +514,7 @@ static hipError_t launch_one(const RowArgs &a, hipStream_t s) {
   typedef Geometry<LOG2N> G;
   if (a.rows <= 0) return hipSuccess;
 #if BFP_MODE_ID == 3
-  if constexpr (LOG2N == 12 && (V & (V_TRANS | V_ADAPT)) == 0) {
+  if constexpr (LOG2N == 12 && (V & (V_TRANS | V_ADAPT | V_RAMP)) == 0) {
     if (a.engine == 0) return launch_mfma<OP, V, OUT32>(a, s);
   }
 #endif
@@ -521,6 +555,12 @@ static hipError_t launch_size(int op, bool out32, const RowArgs &a, hipStream_t 
       if (conj) return launch_one<LOG2N, OP_INV, V_CONJ, false>(a, s);
       return launch_one<LOG2N, OP_INV, V_PLAIN, false>(a, s);
     case OP_COMPRESS:
+      if (a.flags & KF_RAMP) {
+        if (out32 || ph || naive || conj || a.ent_partial || (a.flags & (KF_TRANSPOSED | KF_ADAPT)) ||
+            !a.shift)
+          return hipErrorInvalidValue;
+        return launch_one<LOG2N, OP_COMPRESS, V_RAMP, false>(a, s);
+      }
       if (a.flags & KF_ADAPT) {
         if (out32 || ph || naive || conj || a.ent_partial || (a.flags & KF_TRANSPOSED) || !a.row_exp)
           return hipErrorInvalidValue;

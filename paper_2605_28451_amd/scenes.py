@@ -260,3 +260,69 @@ def decode(a: np.ndarray, fmt: str) -> np.ndarray:
 def quantize(x: np.ndarray, fmt: str) -> np.ndarray:
     """The storage-rounded values as complex128 (what both sides consume)."""
     return decode(encode(x, fmt), fmt)
+
+
+# ------------------------------------------------- range cell migration ----
+# Normalised range-Doppler geometry with true hyperbolic migration (the RCMC
+# step of the paper's pipeline, Sec. VI; its scene states no geometry).  In
+# range bins: slant range R(m) = sqrt(rho0^2 + kappa^2 m^2) at pulse offset m
+# from closest approach; two-way phase -2 pi mu R(m) with mu = 2 dr / lambda
+# (cycles of two-way path per range bin).  kappa^2 = rho_ref (b_a / A) / mu
+# gives, at the reference range, the azimuth chirp of the unmigrated scene
+# (b_a over A pulses); the migration at the aperture edge is then
+# A b_a / (8 mu) range bins (6.4 for A = 512, b_a = 0.8, mu = 8).  A far
+# reference range (rho_ref = 1e6 bins) keeps the azimuth FM rate and the
+# migration within 0.1% over the swath, so one azimuth filter and one
+# migration curve (range-invariant RCMC at the reference range) apply.
+
+@dataclass
+class MigrationScene:
+    echo: np.ndarray                 # [pulse][range] complex128
+    range_replica: np.ndarray        # length n_range, zero-padded chirp
+    azimuth_replica: np.ndarray      # length n_pulse, centred on 0, hyperbolic phase at rho_ref
+    rcmc_shift: np.ndarray           # per Doppler bin k: range shift (bins) that undoes the migration
+    targets: List[Tuple[int, int]]   # (range start at closest approach, azimuth centre)
+    migration_edge_bins: float       # migration at the aperture edge
+
+
+def migration_scene(seed: int = 7, n: int = 4096, length: int = 1024, aperture: int = 512,
+                    ranges=(1536, 2048, 2560), azimuths=(1024, 2048, 3072), mu: float = 8.0,
+                    rho_ref: float = 1.0e6, b_num: int = 4, b_den: int = 5,
+                    snr_db: float = 20.0) -> MigrationScene:
+    """Raw echo [pulse][range] of unit point targets with hyperbolic range
+    migration.  A target (range start d, azimuth centre c) sits at closest
+    range rho0 = rho_ref + d - n/2; at pulse m (|m - c| < A/2) its echo is the
+    range chirp delayed by R - rho0 bins beyond d (sampled from the analytic
+    chirp at fractional delay) times exp(-2 pi i mu (R - rho0))."""
+    rng = np.random.default_rng(seed)
+    b = b_num / b_den
+    kappa2 = rho_ref * (b / aperture) / mu
+    echo = np.zeros((n, n), dtype=np.complex128)
+    k = np.arange(n, dtype=np.float64)
+    for d in ranges:
+        rho0 = rho_ref + d - n // 2
+        for c in azimuths:
+            for m in range(c - aperture // 2, c + aperture // 2):
+                dm = m - c
+                R = np.sqrt(rho0 * rho0 + kappa2 * dm * dm)
+                delay = d + (R - rho0)
+                t = k - delay                       # chirp time in samples
+                on = (t >= 0.0) & (t < length)
+                tc = t[on] - length / 2.0
+                echo[m % n, on] += np.exp(1j * np.pi * b * tc * tc / length) * \
+                    np.exp(-2j * np.pi * mu * (R - rho0))
+    echo += awgn(rng, (n, n), snr_db)
+    # azimuth replica at the reference range, centred on pulse 0
+    mm = np.arange(-aperture // 2, aperture // 2, dtype=np.float64)
+    Rr = np.sqrt(rho_ref * rho_ref + kappa2 * mm * mm)
+    g = np.zeros(n, dtype=np.complex128)
+    g[np.arange(-aperture // 2, aperture // 2) % n] = np.exp(-2j * np.pi * mu * (Rr - rho_ref))
+    # migration per Doppler bin: a target seen at Doppler f (cycles/pulse)
+    # sits at range rho / D(f), D = sqrt(1 - (f / (mu kappa))^2)
+    f = np.fft.fftfreq(n)
+    D = np.sqrt(1.0 - (f / (mu * np.sqrt(kappa2))) ** 2)
+    shift = rho_ref * (1.0 / D - 1.0)
+    return MigrationScene(echo=echo, range_replica=range_replica_padded(n, length, b_num, b_den),
+                          azimuth_replica=g, rcmc_shift=shift,
+                          targets=[(d, c) for d in ranges for c in azimuths],
+                          migration_edge_bins=float(aperture * b / (8.0 * mu)))

@@ -257,3 +257,76 @@ def test_azimuth_phase_correction_matches_oracle():
     img = _gpu_frame(sc, "fp16_fp32", phase=phi)
     ref = _oracle_frame(sc, "fp16_fp32", phase=phi)
     assert metrics.sqnr_db(ref, img, align=True) >= 45.0
+
+
+# ------------------------------------------ range cell migration (RCMC) ----
+RCMC_SQNR_MIN = {"fp32": 110.0, "fp16_fp32": 60.0, "fp16_mul_fp32_acc": 58.0, "fp16": 52.0,
+                 "e4m3": 12.0, "e5m2": 8.0}
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp16_fp32", "fp16_mul_fp32_acc", "fp16", "e4m3"])
+@pytest.mark.parametrize("n,rows", [(4096, 48), (1024, 96)])
+def test_rcmc_compress_matches_oracle(mode, n, rows):
+    # Doppler rows of range data, each compressed and moved by its own
+    # fractional shift (negative, zero and beyond the migration range)
+    need_gpu()
+    announce(f"rcmc compress mode={mode} n={n}")
+    fmt = api.storage_format(mode)
+    rng = np.random.default_rng(12)
+    scale = 0.125 if mode in ("e4m3", "e5m2") else 1.0
+    x = scenes.quantize(scale * scenes.gaussian_rows(13, rows, n), fmt)
+    shift = np.concatenate([[0.0, 3.0, -5.5], rng.uniform(-12.0, 12.0, rows - 3)]).astype(np.float32)
+    h = scenes.range_replica_padded(n, n // 4)
+    Hq = scenes.quantize(oracle.matched_filter(h, n), api.filter_format(mode))
+    plan = api.FFTPlan(n, rows, mode, flags=api.FLAG_CHECK_FINITE)
+    y = plan.range_compress_rcmc(upload(x, fmt), api.filter_tensor(h, n, mode),
+                                 torch.tensor(shift, device="cuda"))
+    got = download(y, fmt)
+    ref = oracle.rcmc_compress(x, Hq, shift.astype(np.float64))
+    s = metrics.sqnr_db(ref, got)
+    print(f"mode={mode} n={n} rcmc compress SQNR {s:.2f} dB")
+    assert plan.nonfinite() == 0
+    assert s >= RCMC_SQNR_MIN[mode]
+
+
+def _gpu_rcmc_frame(sc, mode):
+    """azimuth FFT -> corner turn -> migration-corrected range compression
+    per Doppler bin -> corner turn -> azimuth BFP inverse with H_a."""
+    fmt = api.storage_format(mode)
+    npul, nr = sc.echo.shape
+    aplan = api.FFTPlan(npul, nr, mode, flags=api.FLAG_CHECK_FINITE)
+    rplan = api.FFTPlan(nr, npul, mode, flags=api.FLAG_CHECK_FINITE)
+    echo = upload(scenes.quantize(sc.echo, fmt), fmt)
+    spec = aplan.forward(api.corner_turn(echo, fmt))              # [range][Doppler]
+    rd = api.corner_turn(spec, fmt)                               # [Doppler][range]
+    shift = torch.tensor(sc.rcmc_shift.astype(np.float32), device="cuda")
+    rc = rplan.range_compress_rcmc(rd, api.filter_tensor(sc.range_replica, nr, mode), shift)
+    img = aplan.inverse_bfp(api.corner_turn(rc, fmt), api.filter_tensor(sc.azimuth_replica, npul, mode))
+    out = download(img, fmt)
+    assert rplan.nonfinite() == 0 and aplan.nonfinite() == 0
+    return out
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp16_fp32", "fp16"])
+def test_rcmc_frame_4096_matches_oracle_metrics(mode):
+    need_gpu()
+    announce(f"RCMC frame 4096x4096 mode={mode}")
+    sc = scenes.migration_scene()
+    img = _gpu_rcmc_frame(sc, mode)
+    fmt, ffmt = api.storage_format(mode), api.filter_format(mode)
+    Hr = scenes.quantize(oracle.matched_filter(sc.range_replica, 4096), ffmt)
+    Ha = scenes.quantize(oracle.matched_filter(sc.azimuth_replica, 4096), ffmt)
+    ref = oracle.rda_rcmc_image(scenes.quantize(sc.echo, fmt), Hr, Ha,
+                                sc.rcmc_shift.astype(np.float32).astype(np.float64))
+    s = metrics.sqnr_db(ref, img, align=True)
+    print(f"mode={mode} RCMC frame SQNR {s:.2f} dB")
+    assert np.all(np.isfinite(img))
+    assert s >= FRAME_SQNR_MIN[mode]
+    for (r0, a0) in sc.targets:
+        mg = metrics.point_target(img, r0, a0, noise_patch=(r0 + 300, a0 + 300))
+        mo = metrics.point_target(ref, r0, a0, noise_patch=(r0 + 300, a0 + 300))
+        assert mg["peak_rc"] == mo["peak_rc"] == (r0, a0)
+        for k in ("pslr_range", "pslr_azimuth", "islr_range", "islr_azimuth", "snr"):
+            assert abs(mg[k] - mo[k]) <= 0.1, (r0, a0, k, mg[k], mo[k])
+        for k in ("irw_range", "irw_azimuth"):
+            assert abs(mg[k] - mo[k]) <= 0.02, (r0, a0, k, mg[k], mo[k])

@@ -88,3 +88,19 @@ def test_weighted_replicas_taper_the_support_only():
     m = np.arange(-256, 256)
     assert np.array_equal(g[m % n], g0[m % n] * wa)
     assert np.count_nonzero(g) == 512
+
+
+def test_migration_scene_geometry():
+    sc = scenes.migration_scene(ranges=(2048,), azimuths=(2048,))
+    assert abs(sc.migration_edge_bins - 6.4) < 1e-12
+    f = np.fft.fftfreq(4096)
+    # the migration curve is even in Doppler, zero at f = 0 and about
+    # A b_a / (8 mu) = 6.4 bins at the band edge f = 0.4
+    assert sc.rcmc_shift[0] == 0.0
+    assert np.allclose(sc.rcmc_shift[1:2048], sc.rcmc_shift[:2048:-1][:2047])
+    k = int(np.argmin(np.abs(f - 0.4)))
+    assert abs(sc.rcmc_shift[k] - 6.4) < 0.01
+    # the echo holds the delayed chirp: at closest approach it starts at the
+    # target's range start, at the aperture edge 6.4 bins later
+    p0 = sc.echo[2048] - 0  # closest approach
+    assert np.abs(p0[2048]) > 0.5 and np.abs(p0[2040]) < 0.5
