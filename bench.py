@@ -439,12 +439,14 @@ def cpu_baseline(sample_in, replica, n, sample_out):
     }, sq, sq_raw
 
 
-def bench_rcmc_frame(mode, steps, warmup, n_frames=4):
+def bench_rcmc_frame(mode, steps, warmup, n_frames=4, streams=1):
     """4096x4096 range-Doppler frame with range cell migration correction:
     corner turn, azimuth FFT, corner turn, migration-corrected range
     compression per Doppler bin, corner turn, azimuth BFP inverse with H_a
     (12 passes over 64 MiB in FP16), n_frames rotating buffer sets, one HIP
-    graph per replay; plus the focus metrics of the first image."""
+    graph per replay (streams > 1: frames dealt to that many streams forked
+    and joined inside the graph, as in bench_sar_frame); plus the focus
+    metrics of the first image."""
     import torch
     from paper_2605_28451_amd import api, scenes, metrics
     fmt = api.storage_format(mode)
@@ -474,10 +476,17 @@ def bench_rcmc_frame(mode, steps, warmup, n_frames=4):
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
+    side = [torch.cuda.Stream() for _ in range(streams - 1)]
     with torch.cuda.stream(s):
         with torch.cuda.graph(g, stream=s):
+            lanes = [s] + side
+            for q in side:
+                q.wait_stream(s)
             for i in range(n_frames):
-                frame(i)
+                with torch.cuda.stream(lanes[i % streams]):
+                    frame(i)
+            for q in side:
+                s.wait_stream(q)
     torch.cuda.current_stream().wait_stream(s)
     g.replay()
     torch.cuda.synchronize()
@@ -496,7 +505,8 @@ def bench_rcmc_frame(mode, steps, warmup, n_frames=4):
     aplan.close()
     rplan.close()
     torch.cuda.empty_cache()
-    return {"mode": mode, "ms_per_frame": round(ms, 5), "frames_per_s": round(1e3 / ms, 1),
+    return {"mode": mode, "concurrent_streams": streams, "ms_per_frame": round(ms, 5),
+            "frames_per_s": round(1e3 / ms, 1),
             "hbm_gbs": round(bytes_frame / (ms * 1e-3) / 1e9, 1), "bytes_per_frame": bytes_frame,
             "migration_edge_bins": sc.migration_edge_bins,
             "pslr_range_db_mean": round(float(np.mean([p["pslr_range"] for p in pts])), 3),
@@ -724,6 +734,8 @@ def main():
         log("RCMC frame 4096x4096 (hyperbolic migration 6.4 bins), fp16 and fp32 (graph)")
         out["sar_frame_4096_rcmc"] = {m: bench_rcmc_frame(m, args.steps, args.warmup)
                                       for m in ("fp16", "fp32")}
+        out["sar_frame_4096_rcmc"]["fp16_2_streams"] = bench_rcmc_frame("fp16", args.steps, args.warmup,
+                                                                        streams=2)
         log("uneven batch 20000 transforms fp16")
         ub = bench_uneven("fp16", args.steps, args.warmup)
         out["uneven_20000"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in ub.items()}

@@ -54,14 +54,12 @@ enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4, V_TRANS = 8, 
 // bin) multiplies its spectrum by H[k] exp(+2 pi i k' s_r / N), k' the
 // signed bin (k - N for k >= N/2), which is the band-limited (periodic sinc)
 // interpolation moving the compressed row s_r bins toward smaller range.
-// The phase is reduced to [-1/2, 1/2] cycles in FP32 and evaluated by
-// sincospif; the product with H is formed in FP32 and rounded once to the
-// filter type.
-template <int LOG2N>
-__device__ __forceinline__ c32 rcmc_ramp(unsigned k, float s) {
-  constexpr int N = 1 << LOG2N;
-  const float kk = (float)((int)k - (k >= (unsigned)(N / 2) ? N : 0));
-  float cyc = kk * s * (1.0f / N);
+// A thread's bins are k' = t + T e (e < E/2) and t + T e - N (e >= E/2), so
+// its phasors are base . step^e (times a wrap phasor for the upper half):
+// three sincospif per row (phases reduced to [-1/2, 1/2] cycles) and FP32
+// complex products (the error of 16 products stays below 1e-6); the product
+// with H is formed in FP32 and rounded once to the filter type.
+__device__ __forceinline__ c32 cycles_phasor(float cyc) {
   cyc -= rintf(cyc);
   float sn, cs;
   sincospif(2.0f * cyc, &sn, &cs);
@@ -293,13 +291,18 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
       for (int e = 0; e < E; ++e) v[e] = conj_scale(v[e], sc);
     } else if constexpr (ramp) {
       const float sr = active ? a.shift[row] : 0.0f;
+      c32 r = cycles_phasor((float)tt * sr * (1.0f / N));
+      const c32 step = cycles_phasor(sr * ((float)T / N));
+      const c32 wrap = cycles_phasor(-sr);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
+        if (e == E / 2) r = cmul(r, wrap);
         Filt h;
         if constexpr (kHoist) h = hf[e];
         else h = f[tt + T * e];
-        filt_from_c32(cmul(to_c32(h), rcmc_ramp<LOG2N>(tt + T * e, sr)), h);
+        filt_from_c32(cmul(to_c32(h), r), h);
         v[e] = conj_pow2<K>(M::fmul(v[e], h));
+        r = cmul(r, step);
       }
     } else if (OP == OP_COMPRESS || f) {
 #pragma unroll
