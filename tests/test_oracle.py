@@ -366,3 +366,34 @@ def test_rcmc_focuses_migrating_targets():
             assert abs(m[k] - 1.107) <= 0.03, (r0, a0, k, m[k])
         u = metrics.point_target(raw, r0, a0)
         assert u["irw_azimuth"] > 2.0 * m["irw_azimuth"] and u["pslr_range"] > m["pslr_range"] + 3.0
+
+
+def test_magnitude_budget_closed_forms():
+    # The cascade of Sec. IV-B: each stage's output magnitude bounds the next
+    # stage's input, and with |H| <= 1 every intermediate of the chains stays
+    # far below the FP16 limit 65504.  Closed forms: a unit target's
+    # range-compressed peak is sum|h|^2 / max|DFT h| = L / max|DFT h|
+    # (Parseval), the focused image peak the product of that with
+    # A / max|DFT g| for the azimuth replica; the forward spectrum obeys
+    # |X| <= N max|x|.
+    n, L, A = 4096, 1024, 512
+    rs = scenes.range_scene(seed=2, n_pulses=64)
+    Mr = np.abs(oracle.fft(rs.replica[None])[0]).max()
+    X = oracle.fft(rs.echo)
+    assert np.abs(X).max() <= n * np.abs(rs.echo).max()
+    Hr = oracle.matched_filter(rs.replica, n)
+    rc = oracle.compress(rs.echo, Hr)
+    # each of the 5 targets peaks at its delay at L / max|DFT h| (about 24)
+    for d in rs.delays:
+        assert abs(np.abs(rc[:, d]).mean() - L / Mr) <= 0.02 * L / Mr
+    assert np.abs(X * Hr[None]).max() / n < 1.0 and np.abs(rc).max() < 64.0
+    sc = scenes.sar_scene(seed=3)
+    Ma = np.abs(oracle.fft(sc.azimuth_replica[None])[0]).max()
+    Ha = oracle.matched_filter(sc.azimuth_replica, n)
+    img, rct = oracle.sar_image(sc.echo, Hr, Ha, return_rc=True)
+    peak = (L / Mr) * (A / Ma)
+    for (r0, a0) in sc.targets:
+        assert abs(np.abs(img[r0, a0]) - peak) <= 0.02 * peak
+    # the largest input of the azimuth stage (three targets share a range
+    # bin) and every output stay below 4096, far inside FP16
+    assert np.abs(oracle.fft(rct)).max() < 4096.0 and np.abs(img).max() < 4096.0
