@@ -249,9 +249,9 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
     concurrently (frame k's memory-bound corner turn beside frame k+1's
     compressions); each frame's three steps stay in order on its stream."""
     import torch
-    from paper_2605_28451_amd import api, scenes
+    from paper_2605_28451_amd import api
     fmt = api.storage_format(mode)
-    sc = scenes.sar_scene(seed=3)
+    sc = _sar_scene()
     n = 4096
     echo0 = api.to_device(sc.echo, fmt)
     echoes = [echo0] + [echo0.clone() for _ in range(n_frames - 1)]
@@ -440,6 +440,61 @@ def cpu_baseline(sample_in, replica, n, sample_out):
 
 
 _MIGRATION_SCENE = []
+_SAR_SCENE = []
+
+
+def _sar_scene():
+    """The 4096x4096 point-target frame (seed 3), generated once per process."""
+    if not _SAR_SCENE:
+        from paper_2605_28451_amd import scenes
+        _SAR_SCENE.append(scenes.sar_scene(seed=3))
+    return _SAR_SCENE[0]
+
+
+def cpu_oracle_workloads(reps=3):
+    """Context beside the CPU baseline: the FP64 oracle as it stands (all host
+    threads) on the other workloads the GPU path is timed on, best of `reps`:
+    the 64 x 4096 BFP round trip (forward, then normalised inverse), one
+    4096 x 4096 range-Doppler frame, and the 20,000-transform uneven batch
+    (transforms grouped by length and direction before the timed calls)."""
+    import numpy as np
+    import oracle
+    from paper_2605_28451_amd import scenes
+
+    def best(fn):
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            t.append(time.perf_counter() - t0)
+        return min(t)
+
+    res = {"threads": oracle.num_threads()}
+    x = scenes.quantize(scenes.gaussian_rows(1, 64, 4096), "fp16")
+    dt = best(lambda: oracle.fft(oracle.fft(x), inverse=True))
+    res["round_trip_64x4096"] = {"ms": round(dt * 1e3, 3),
+                                 "gflops": round(fft_flops(4096, 128) / dt / 1e9, 2)}
+    sc = _sar_scene()
+    echo = scenes.quantize(sc.echo, "fp16")
+    Hr = scenes.quantize(oracle.matched_filter(sc.range_replica, 4096), "fp16")
+    Ha = scenes.quantize(oracle.matched_filter(sc.azimuth_replica, 4096), "fp16")
+    dt = best(lambda: oracle.sar_image(echo, Hr, Ha))
+    res["sar_frame_4096"] = {"ms": round(dt * 1e3, 1), "frames_per_s": round(1.0 / dt, 2),
+                             "gflops": round(fft_flops(4096, 4 * 4096) / dt / 1e9, 2)}
+    ub = scenes.uneven_batch(seed=4, count=20000)
+    xq = scenes.quantize(ub.x, "fp16")
+    groups = []
+    for e in np.unique(ub.log2n):
+        for d in (0, 1):
+            idx = np.nonzero((ub.log2n == e) & (ub.inverse == d))[0]
+            if idx.size:
+                n = 1 << int(e)
+                rows = np.stack([xq[o:o + n] for o in ub.offsets[idx]])
+                groups.append((rows, bool(d)))
+    dt = best(lambda: [oracle.fft(r, inverse=d) for r, d in groups])
+    flops = float(np.sum(5.0 * (1 << ub.log2n.astype(np.int64)) * ub.log2n))
+    res["uneven_20000"] = {"ms": round(dt * 1e3, 1), "gflops": round(flops / dt / 1e9, 2)}
+    return res
 
 
 def _migration_scene():
@@ -558,7 +613,7 @@ def weighted_frame_metrics(mode, taper):
     image quality is reported."""
     import torch
     from paper_2605_28451_amd import api, scenes, metrics
-    sc = scenes.sar_scene(seed=3)
+    sc = _sar_scene()
     n = 4096
     fmt = api.storage_format(mode)
     kind, rest = taper[0], taper[1:]
@@ -764,6 +819,9 @@ def main():
             "peak_power_gain_db": round(float(10 * np.log10(np.mean([p["peak_power"] for p in after]) /
                                                           np.mean([p["peak_power"] for p in before]))), 2),
         }
+        if not args.no_cpu:
+            log("cpu oracle on the other workloads (context)")
+            out["cpu_baseline"]["other_workloads"] = cpu_oracle_workloads()
     print(json.dumps(out), flush=True)
 
 
