@@ -128,10 +128,8 @@ void free_plan(bfp_plan p) {
   (void)hipFree(p->nonfinite);
   (void)hipFree(p->phasor);
   (void)hipFree(p->items);
-  (void)hipFree(p->offsets_d);
-  (void)hipFree(p->inverse_d);
+  (void)hipFree(p->xform_d);
   (void)hipFree(p->queue);
-  (void)hipFree(p->order_d);
   if (p->tw32 != p->tw) (void)hipFree(p->tw32);
   (void)hipFree(p->ent_partial);
   (void)hipFree(p->pg_partial);

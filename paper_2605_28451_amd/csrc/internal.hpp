@@ -59,12 +59,13 @@ int pass_radix(int log2n, int p);
 struct UnevenArgs {
   const void *in;
   void *out;
-  const int4 *items;          // (first position in order[], count, log2n, 0) per item
-  const int *order;           // transform indices grouped by length, longest first
-  const long long *offsets;   // element offset of each transform
-  const unsigned char *inverse;
+  const int4 *items;          // (first position in xform[], count, log2n, 0) per item
+  // one word per transform, grouped by length, longest first:
+  // (element offset << 1) | inverse
+  const long long *xform;
   int n_items;
-  unsigned *queue;            // work counter, zeroed by the launcher's reset kernel
+  unsigned *queue;            // work counter (items claimed after the first
+                              // gridDim.x), zeroed by the launcher's reset kernel
   const void *const *tw;      // per-size twiddle tables, index log2n - 8
   unsigned flags;
   unsigned long long *nonfinite;

@@ -21,11 +21,9 @@ struct bfp_plan_s {
   long long total = 0;
   std::vector<long long> offsets;
   int4 *items = nullptr;
-  long long *offsets_d = nullptr;
-  unsigned char *inverse_d = nullptr;
+  long long *xform_d = nullptr;               // (offset << 1) | inverse, item order
   int n_items = 0;
   unsigned *queue = nullptr;
-  int *order_d = nullptr;
   int grid = 0;
   // tuning knobs (fft_plan_set_tuning / fft_autotune)
   int tune_engine = 1;     // 0: matrix cores where available, 1: vector ALU (default)

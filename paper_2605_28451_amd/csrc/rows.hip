@@ -14,6 +14,8 @@
 // -> FFT -> conj, entirely in registers/LDS: one HBM read and one HBM write
 // per row.  The forward FFT's last pass leaves X[k] at the positions the
 // inverse's first pass reads, so no data moves between the two transforms.
+#include <type_traits>
+
 #include "fft_engine.hpp"
 #include "fft_mfma.hpp"
 #include "internal.hpp"
@@ -151,12 +153,16 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   const Tw *tw = static_cast<const Tw *>(a.tw);
   // A 4-byte filter (FP16 pairs) is the same for every row: its E values
   // per thread are loaded once, ahead of the row loop, so no row waits on
-  // them.  Wider filters are read per row to keep registers free.
+  // them.  Wider filters are read per row to keep registers free, and so is
+  // the pure-FP16 filter at N >= 8192: without its E registers those kernels
+  // fit 8 wavefronts per SIMD (two 1024-thread workgroups per CU at
+  // N = 16384 instead of one).
   const Filt *f = static_cast<const Filt *>(a.filter);
   // row I/O through load_row / store_row (not in the pipelined kernel; FP8
   // rows keep the per-element decode, which needs fewer registers)
   constexpr bool kRowIo = !PIPE && sizeof(Store) >= 4;
-  constexpr bool kHoist = sizeof(Filt) == 4 && OP != OP_FWD;
+  constexpr bool kHoist = sizeof(Filt) == 4 && OP != OP_FWD &&
+                          (LOG2N <= 12 || !std::is_same<M, ModeFP16>::value);
   Filt hf[kHoist ? E : 1];
   if constexpr (kHoist) {
     if (f) {

@@ -54,9 +54,9 @@ __device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typenam
   long long off = 0;
   bool inv = false;
   if (active) {
-    const int idx = a.order[d.x + local];
-    off = a.offsets[idx];
-    inv = a.inverse[idx] != 0;
+    const long long w = a.xform[d.x + local];
+    off = w >> 1;
+    inv = (w & 1) != 0;
   }
   Comp v[E];
   if (active) {
@@ -102,11 +102,10 @@ template <class M>
 __global__ void __launch_bounds__(UNEVEN_WG, uneven_waves_per_simd<M>()) uneven_kernel(UnevenArgs a) {
   __shared__ typename M::Lds lds[UNEVEN_LDS];
   __shared__ int item_s;
-  for (;;) {
-    if (threadIdx.x == 0) item_s = (int)atomicAdd(a.queue, 1u);
-    __syncthreads();
-    const int it = item_s;
-    __syncthreads();  // every thread has read item_s before it is rewritten
+  // the first item of each workgroup is its own index (no queue round trip
+  // before the first load); later items come from the counter, past the
+  // grid's first gridDim.x
+  for (int it = blockIdx.x;;) {
     if (it >= a.n_items) break;
     const int4 d = a.items[it];
     // The thread index, made opaque per item: otherwise the compiler hoists
@@ -124,7 +123,10 @@ __global__ void __launch_bounds__(UNEVEN_WG, uneven_waves_per_simd<M>()) uneven_
       case 14: uneven_item<M, 14>(a, d, lds, tid); break;
       default: break;
     }
-    __syncthreads();  // LDS of this item is free before the next one
+    if (threadIdx.x == 0) item_s = (int)(gridDim.x + atomicAdd(a.queue, 1u));
+    __syncthreads();  // LDS of this item is free, and item_s is written
+    it = item_s;
+    __syncthreads();  // every thread has read item_s before it is rewritten
   }
 }
 

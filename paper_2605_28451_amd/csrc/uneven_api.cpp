@@ -98,18 +98,15 @@ int fft_plan_uneven(bfp_plan *out, int count, const int *log2n, const unsigned c
     s = e;
   }
   p->n_items = (int)items.size();
-  std::vector<unsigned char> inv(inverse, inverse + count);
+  // each transform's offset and direction in one word, in item order, so a
+  // workgroup reaches its data after a single dependent load
+  std::vector<long long> xform(count);
+  for (int s = 0; s < count; ++s)
+    xform[s] = (p->offsets[order[s]] << 1) | (inverse[order[s]] ? 1 : 0);
 
   int st = BFP_OK;
-  std::vector<long long> offs = p->offsets;
   if (!st) st = upload(items, &p->items);
-  if (!st) {
-    int *ord = nullptr;
-    st = upload(order, &ord);
-    p->order_d = ord;
-  }
-  if (!st) st = upload(offs, &p->offsets_d);
-  if (!st) st = upload(inv, &p->inverse_d);
+  if (!st) st = upload(xform, &p->xform_d);
   std::vector<void *> ptrs(7, nullptr);
   for (int l = 8; l <= 14 && !st; ++l) {
     st = table_for(l, prec, &p->tw_sizes[l - 8]);
@@ -169,9 +166,7 @@ int fft_exec_uneven(bfp_plan p, const void *in, void *out, void *stream) {
   a.in = in;
   a.out = out;
   a.items = p->items;
-  a.order = p->order_d;
-  a.offsets = p->offsets_d;
-  a.inverse = p->inverse_d;
+  a.xform = p->xform_d;
   a.n_items = p->n_items;
   a.queue = p->queue;
   a.tw = p->tw_ptrs_d;
