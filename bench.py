@@ -742,6 +742,16 @@ def main():
                 "(2 rotating sets, 1 GiB working set)")
             r = bench_fft("fp16", 16384, n, args.steps, args.warmup, inverse=inv)
             fft[name] = {k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}
+        by_n = {}
+        for e in range(8, 15):
+            nn = 1 << e
+            log(f"plain forward / BFP inverse FFT n={nn} batch={(1 << 25) // nn} mode=fp16")
+            for inv in (False, True):
+                r = bench_fft("fp16", (1 << 25) // nn, nn, args.steps, args.warmup, inverse=inv)
+                by_n[f"{nn}_{'inverse_bfp' if inv else 'forward'}"] = {
+                    "rows": r["rows"], "us_per_launch": round(r["ms_per_launch"] * 1e3, 2),
+                    "gflops": round(r["gflops"], 1), "hbm_frac": round(r["hbm_frac"], 4)}
+        out["fft_fp16_by_n"] = by_n
         log("plain forward FFT n=4096 batch=64 (latency-bound shape)")
         r = bench_fft("fp16", 64, n, args.steps, args.warmup, min_bytes=0)
         fft["fp16_batch64"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}

@@ -38,6 +38,40 @@ def test_range_compression_matches_oracle(mode):
         assert np.argmax(np.abs(rc[0, max(d - 3, 0):d + 4])) + max(d - 3, 0) == d
 
 
+@pytest.mark.parametrize("mode", ["fp32", "fp16", "fp16_fp32", "fp16_mul_fp32_acc"])
+@pytest.mark.parametrize("n", [256, 512, 1024, 2048, 4096, 8192, 16384])
+def test_compression_and_filtered_inverse_all_sizes(mode, n):
+    # fused compression and the filtered BFP inverse at every length, with a
+    # ragged batch (not a multiple of the transforms per workgroup); the
+    # large lengths read the filter per row in pure FP16, the others hold it
+    # in registers
+    need_gpu()
+    rows = 3 if n <= 1024 else 2
+    announce(f"compression + filtered inverse n={n} rows={rows} mode={mode}")
+    fmt = api.storage_format(mode)
+    ffmt = api.filter_format(mode)
+    sc = scenes.range_scene(seed=2, n_pulses=rows, n=n, length=n // 4)
+    echo = scenes.quantize(sc.echo, fmt)
+    H = scenes.quantize(oracle.matched_filter(sc.replica, n), ffmt)
+    plan = api.FFTPlan(n, rows, mode, flags=api.FLAG_CHECK_FINITE)
+    Hd = api.filter_tensor(sc.replica, n, mode)
+    bar = RC_SQNR_MIN[mode] - (3.0 if n > 4096 else 0.0)
+    rc = download(plan.range_compress(upload(echo, fmt), Hd), fmt)
+    s = sqnr_db(oracle.compress(echo, H), rc, align=True)
+    assert s >= bar, (n, mode, s)
+    # every target is a peak of its neighbourhood (equal amplitudes: no global order)
+    for d in sc.delays:
+        lo = max(int(d) - 2, 0)
+        assert lo + int(np.argmax(np.abs(rc[0, lo:int(d) + 3]))) == d, (n, mode, d)
+    # BFP inverse of a spectrum-domain input times the filter: IDFT(z . H)
+    g = np.random.default_rng(n + 9).standard_normal((2, rows, n))
+    z = scenes.quantize((g[0] + 1j * g[1]) * np.sqrt(n), fmt)
+    y = download(plan.inverse_bfp(upload(z, fmt), Hd), fmt)
+    si = sqnr_db(oracle.fft(z * H, inverse=True), y, align=True)
+    assert si >= bar, (n, mode, si)
+    assert plan.nonfinite() == 0
+
+
 @pytest.mark.parametrize("mode", ["fp16", "fp16_fp32"])
 def test_range_compression_naive_overflows(mode):
     need_gpu()
