@@ -657,7 +657,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
-              "(batches and SAR frames shard by row/frame with no exchange; see the design notes)",
+              "(batches and SAR frames would shard by row or frame, with no exchange between GPUs)",
               file=sys.stderr)
         sys.exit(2)
     import torch
