@@ -69,7 +69,7 @@ def test_traffic_summary_scales_each_counter_by_the_copy(tmp_path, monkeypatch, 
     assert m["traffic_bytes"] == (16200 * 2 + 32768) * 1024
     assert m["fetch_factor"] == 2.0 and m["write_factor"] == 1.0
     assert rec["kernel_source_sha256"] == bench.kernel_source_sha256()
-    assert "(0.995 x algorithmic 67108864 B)" in capsys.readouterr().out
+    assert "(0.994 x algorithmic 67108864 B)" in capsys.readouterr().out
 
 
 def test_measured_traffic_only_for_the_sources_it_was_taken_on(tmp_path, monkeypatch):
