@@ -169,6 +169,19 @@ def autofocus(rc_t, Ha, phi, want_image: bool = False):
     return (E, g, img) if want_image else (E, g)
 
 
+def adam_step(phi, g, m, v, k, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba, 2015, Algorithm 1) in FP64, for step
+    number k >= 1: the moment estimates, their bias corrections, and the
+    update of phi.  Returns (phi, m, v) as new arrays."""
+    phi = np.asarray(phi, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** k)
+    v_hat = v / (1.0 - beta2 ** k)
+    return phi - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
 def adaptive_exponent(z, n: int):
     """Per-row exponent of the adaptive block shift (the per-block exponents
     of Sec. VIII's future work, as this library defines them): for the

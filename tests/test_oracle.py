@@ -237,6 +237,37 @@ def test_autofocus_gradient_fd_and_invariance():
         assert fd == pytest.approx(g[m], rel=1e-6, abs=1e-10)
 
 
+# Adam (Kingma & Ba, 2015, Algorithm 1) for the autofocus phase.  Pins: the
+# library routine torch.optim.Adam (FP64 on the CPU) over a sequence of
+# gradients, and the closed form under a constant gradient, where the bias
+# corrections make both moment estimates exact: every step moves each
+# element by lr g / (|g| + eps).
+
+def test_adam_matches_torch_optimizer():
+    import torch
+    rng = np.random.default_rng(11)
+    n, lr, betas, eps = 257, 0.3, (0.9, 0.999), 1e-8
+    phi0 = rng.standard_normal(n)
+    grads = [rng.standard_normal(n) * s for s in (1.0, 0.1, 3.0, 0.5, 2.0)]
+    p = torch.tensor(phi0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=lr, betas=betas, eps=eps)
+    phi, m, v = phi0, np.zeros(n), np.zeros(n)
+    for k, g in enumerate(grads, start=1):
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        phi, m, v = oracle.adam_step(phi, g, m, v, k, lr, betas[0], betas[1], eps)
+        np.testing.assert_allclose(phi, p.detach().numpy(), rtol=1e-13, atol=1e-14)
+
+
+def test_adam_constant_gradient_closed_form():
+    g = np.array([2.0, -0.5, 1e-3, -7.0])
+    lr, eps = 0.1, 1e-8
+    phi, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for k in range(1, 6):
+        phi, m, v = oracle.adam_step(phi, g, m, v, k, lr, eps=eps)
+        np.testing.assert_allclose(phi, -k * lr * g / (np.abs(g) + eps), rtol=1e-12)
+
+
 # ---------------------------------------------------- weighted apertures ----
 # Tapers for the weighted matched filters of Sec. VIII (limitations: deeply
 # weighted apertures with sidelobes near -40 dB).  Pins: the library routine
