@@ -351,7 +351,7 @@ def bench_autofocus(steps, lr=0.3):
     import numpy as np
     import torch
     from paper_2605_28451_amd import api, scenes
-    from paper_2605_28451_amd.autofocus import AutofocusPlan, entropy_and_grad
+    from paper_2605_28451_amd.autofocus import AutofocusLoop, AutofocusPlan, entropy_and_grad
     n = 4096
     perr = scenes.autofocus_phase_error(seed=5, n_pulse=n)
     sc = scenes.sar_scene(seed=3, phase_error=perr)
@@ -362,36 +362,39 @@ def bench_autofocus(steps, lr=0.3):
     rct = api.corner_turn(rc, "fp16")
     plan = AutofocusPlan(n, n, mode)
     Ha = api.filter_tensor(sc.azimuth_replica, n, mode)
-    phi = torch.zeros(n, dtype=torch.float32, device="cuda", requires_grad=True)
-    # the fused Adam keeps its step count on the device: no host round trip per step
-    opt = torch.optim.Adam([phi], lr=lr, fused=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run(graph):
+        """`steps` Adam iterations from phase 0 (library kernels only; one
+        captured iteration replayed per step when graph)."""
+        phi = torch.zeros(n, dtype=torch.float32, device="cuda")
+        loop = AutofocusLoop(plan, rct, Ha, phi, lr=lr, graph=graph)
+        E0 = float(loop.entropy())
+        img0 = api.to_host(loop.img, "fp32")
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            loop.step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        E = float(loop.entropy())
+        return ms, E0, E, img0, api.to_host(loop.img, "fp32"), phi
+
+    ms, E0, E, img0, img1, phi_g = run(graph=True)
+    ms_eager, _, E_eager, _, _, phi_e = run(graph=False)
+    # the image, entropy and phase gradient alone (no update), back to back
     img = torch.empty((n, n, 2), dtype=torch.float32, device="cuda")
     stats = torch.empty(3, dtype=torch.float64, device="cuda")
     grad = torch.empty(n, dtype=torch.float32, device="cuda")
-    E0, _, _ = entropy_and_grad(plan, rct, Ha, phi.detach(), img=img, stats=stats, grad=grad)
-    E0 = float(E0)
-    img0 = api.to_host(img, "fp32")
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        E, g, _ = entropy_and_grad(plan, rct, Ha, phi.detach(), img=img, stats=stats, grad=grad)
-        phi.grad = g
-        opt.step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    E, _, _ = entropy_and_grad(plan, rct, Ha, phi.detach(), img=img, stats=stats, grad=grad)
-    img1 = api.to_host(img, "fp32")
-    # the image, entropy and phase gradient alone (no optimizer), back to back
-    ph = phi.detach()
-    e0.record()
-    for _ in range(steps):
-        entropy_and_grad(plan, rct, Ha, ph, img=img, stats=stats, grad=grad)
+        entropy_and_grad(plan, rct, Ha, phi_g, img=img, stats=stats, grad=grad)
     e1.record()
     torch.cuda.synchronize()
     ms_grad = e0.elapsed_time(e1) / steps
-    return {"ms_per_step": ms, "ms_per_gradient": ms_grad, "steps": steps, "lr": lr,
+    return {"ms_per_step": ms, "ms_per_step_eager": ms_eager, "ms_per_gradient": ms_grad,
+            "graph_equals_eager": bool(torch.equal(phi_g, phi_e)), "steps": steps, "lr": lr,
             "entropy_before": E0,
             "entropy_after": float(E), "_img0": img0, "_img1": img1, "_scene": sc}
 
@@ -829,7 +832,10 @@ def main():
         before = [_m.point_target(af["_img0"], r0, a0, search=64) for (r0, a0) in sc.targets]
         after = [_m.point_target(af["_img1"], r0, a0, search=64) for (r0, a0) in sc.targets]
         out["autofocus_4096"] = {
-            "ms_per_step": round(af["ms_per_step"], 4), "ms_per_gradient": round(af["ms_per_gradient"], 4),
+            "ms_per_step": round(af["ms_per_step"], 4), "ms_per_step_eager": round(af["ms_per_step_eager"], 4),
+            "ms_per_gradient": round(af["ms_per_gradient"], 4),
+            "step": "image + entropy, fused phase gradient, Adam (library kernels), one HIP graph replay per step",
+            "graph_equals_eager": af["graph_equals_eager"],
             "steps": af["steps"], "lr": af["lr"],
             "entropy_before": round(af["entropy_before"], 5), "entropy_after": round(af["entropy_after"], 5),
             "pslr_azimuth_db_before": round(float(np.mean([p["pslr_azimuth"] for p in before])), 2),

@@ -321,6 +321,19 @@ int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, co
                            const void *h_az, const float *phase, float *grad_phase, int n_range,
                            void *stream);
 
+/* One Adam step (Kingma & Ba, 2015, Algorithm 1) of the autofocus phase:
+ *   k = *step + 1;  m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2;
+ *   phase -= lr (m / (1 - beta1^k)) / (sqrt(v / (1 - beta2^k)) + eps);  *step = k.
+ * phase, grad, m, v: device, n floats each (m and v zeroed by the caller
+ * before the first step); step: device, one unsigned (zeroed before the
+ * first step).  All state stays on the device, so a whole autofocus
+ * iteration (sar_azimuth_image_entropy, sar_azimuth_phase_grad, this call)
+ * can be captured in a graph and replayed.  n in [1, 2^20]; lr finite and
+ * >= 0; beta1, beta2 in [0, 1); eps finite and > 0; otherwise BFP_EINVAL
+ * before any launch.  Calls on the same state must not overlap. */
+int sar_autofocus_adam(float *phase, const float *grad, float *m, float *v, unsigned *step, int n,
+                       float lr, float beta1, float beta2, float eps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,8 @@ SIGNATURES = {
     "sar_azimuth_image_entropy": (_I, [_P, _P, _P, _P, _P, _I, _P, _P]),
     "sar_entropy_grad": (_I, [_P, _P, _P, _P, _LL, _P]),
     "sar_azimuth_phase_grad": (_I, [_P, _P, _P, _P, _P, _P, _P, _I, _P]),
+    "sar_autofocus_adam": (_I, [_P, _P, _P, _P, _P, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, _P]),
 }
 
 _lib = None

@@ -114,3 +114,71 @@ def entropy_and_grad(plan, rc_t, h_az, phase, img=None, stats=None, grad=None):
     img, stats = plan.image_and_entropy(rc_t, h_az, phase, out=img, stats=stats)
     grad = plan.phase_grad(rc_t, img, h_az, phase, stats=stats, out=grad)
     return stats[2], grad, img
+
+
+class PhaseAdam:
+    """Adam on a device phase vector (Kingma & Ba, 2015), moments and step
+    count on the device (the library's sar_autofocus_adam), so the update
+    needs no host round trip and can be captured in a graph."""
+
+    def __init__(self, phase, lr=0.3, betas=(0.9, 0.999), eps=1e-8):
+        if phase.dtype != torch.float32 or not phase.is_cuda or not phase.is_contiguous():
+            raise ValueError("phase: contiguous float32 device tensor")
+        self.phase = phase
+        self.lr, self.betas, self.eps = float(lr), (float(betas[0]), float(betas[1])), float(eps)
+        self.m = torch.zeros_like(phase)
+        self.v = torch.zeros_like(phase)
+        self.count = torch.zeros(1, dtype=torch.int32, device=phase.device)
+
+    def step(self, grad, stream=None):
+        if grad.dtype != torch.float32 or grad.numel() != self.phase.numel() or not grad.is_cuda:
+            raise ValueError("grad: float32 device tensor of the phase's size")
+        check(_lib.load().sar_autofocus_adam(_ptr(self.phase), _ptr(grad), _ptr(self.m), _ptr(self.v),
+                                             _ptr(self.count), self.phase.numel(), self.lr,
+                                             self.betas[0], self.betas[1], self.eps, _stream(stream)),
+              "sar_autofocus_adam")
+
+
+class AutofocusLoop:
+    """Entropy autofocus by Adam: one iteration is the image and its entropy,
+    the fused phase gradient and the Adam step, all library kernels on the
+    current stream.  With graph=True the iteration is captured once in a HIP
+    graph (buffers preallocated here) and each step() replays it."""
+
+    def __init__(self, plan, rc_t, h_az, phase, lr=0.3, graph=True):
+        n = plan.n
+        rows = rc_t.numel() // (2 * n)
+        self.plan, self.rc_t, self.h_az, self.phase = plan, rc_t, h_az, phase
+        self.opt = PhaseAdam(phase, lr=lr)
+        self.img = torch.empty((rows, n, 2), dtype=torch.float32, device=rc_t.device)
+        self.stats = torch.empty(3, dtype=torch.float64, device=rc_t.device)
+        self.grad = torch.empty(n, dtype=torch.float32, device=rc_t.device)
+        self.graph = None
+        if graph:
+            # warm the launch path on a side stream, then capture one iteration
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(s):
+                with torch.cuda.graph(g, stream=s):
+                    self._iteration()
+            torch.cuda.current_stream().wait_stream(s)
+            self.graph = g
+
+    def _iteration(self):
+        entropy_and_grad(self.plan, self.rc_t, self.h_az, self.phase, img=self.img, stats=self.stats,
+                         grad=self.grad)
+        self.opt.step(self.grad)
+
+    def step(self):
+        """One iteration; afterwards img and stats hold the image and entropy
+        at the phase before the update."""
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self._iteration()
+
+    def entropy(self):
+        """Entropy of the image at the current phase (runs the forward pass)."""
+        self.plan.image_and_entropy(self.rc_t, self.h_az, self.phase, out=self.img, stats=self.stats)
+        return self.stats[2]

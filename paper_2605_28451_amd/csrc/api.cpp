@@ -553,6 +553,19 @@ int sar_entropy_grad(const void *image, const double *stats, const float *scale,
   return e == hipSuccess ? BFP_OK : hip_fail(e, "entropy gradient launch");
 }
 
+int sar_autofocus_adam(float *phase, const float *grad, float *m, float *v, unsigned *step, int n,
+                       float lr, float beta1, float beta2, float eps, void *stream) {
+  if (n < 1 || n > (1 << 20)) return fail(BFP_EINVAL, "n outside [1, 2^20]");
+  if (!phase || !grad || !m || !v || !step) return fail(BFP_EINVAL, "NULL pointer");
+  if (!(lr >= 0.0f && lr < 1e30f)) return fail(BFP_EINVAL, "lr must be finite and >= 0");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+    return fail(BFP_EINVAL, "beta1 and beta2 must lie in [0, 1)");
+  if (!(eps > 0.0f && eps < 1e30f)) return fail(BFP_EINVAL, "eps must be finite and > 0");
+  hipError_t e = bfp::launch_adam(phase, grad, m, v, step, n, lr, beta1, beta2, eps,
+                                  (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "Adam launch");
+}
+
 int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, const double *stats,
                            const void *h_az, const float *phase, float *grad_phase, int n_range,
                            void *stream) {

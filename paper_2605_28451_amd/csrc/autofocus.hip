@@ -127,6 +127,42 @@ hipError_t launch_entropy_grad(const void *img, const double *stats, const float
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ Adam update ----
+
+// One Adam step (Kingma & Ba, 2015, Algorithm 1) on the n per-pulse phases,
+// its moments and step counter kept in device memory, so that consecutive
+// autofocus steps need no host round trip and can be replayed from a graph.
+// One workgroup: the counter is read once, and written back after every
+// element has used it.
+__global__ void __launch_bounds__(1024) adam_kernel(float *phase, const float *grad, float *m, float *v,
+                                                    unsigned *step, int n, float lr, float b1,
+                                                    float b2, float eps) {
+  __shared__ unsigned k_s;
+  if (threadIdx.x == 0) k_s = step[0] + 1u;
+  __syncthreads();
+  // bias corrections 1 - beta^k, in FP64: near k = 1, 1 - beta^k is small
+  // and an FP32 power's last-place error would be a large part of it
+  const float c1 = (float)(1.0 - pow((double)b1, (double)k_s));
+  const float c2 = (float)(1.0 - pow((double)b2, (double)k_s));
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const float g = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g;
+    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    phase[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) step[0] = k_s;
+}
+
+hipError_t launch_adam(float *phase, const float *grad, float *m, float *v, unsigned *step, int n,
+                       float lr, float b1, float b2, float eps, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3(1), dim3(1024), 0, s, phase, grad, m, v, step, n, lr, b1, b2,
+                     eps);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------ phase gradient ----
 
 template <class StoreT, int LOG2N, bool FUSED>

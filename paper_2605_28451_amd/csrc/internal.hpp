@@ -113,6 +113,8 @@ hipError_t launch_entropy_grad(const void *img, const double *stats, const float
                                long long count, hipStream_t s);
 hipError_t launch_phase_grad(bool fp16_storage, int log2n, const PhaseGradArgs &a, bool fused,
                              hipStream_t s);
+hipError_t launch_adam(float *phase, const float *grad, float *m, float *v, unsigned *step, int n,
+                       float lr, float b1, float b2, float eps, hipStream_t s);
 long long phase_grad_scratch_floats(int log2n);
 
 }  // namespace bfp

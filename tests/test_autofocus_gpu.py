@@ -10,8 +10,9 @@ import torch
 
 import oracle
 from paper_2605_28451_amd import api, scenes
-from paper_2605_28451_amd.autofocus import (AutofocusPlan, AzimuthFocus, ImageEntropy,
-                                            entropy_and_grad)
+from paper_2605_28451_amd import _lib
+from paper_2605_28451_amd.autofocus import (AutofocusLoop, AutofocusPlan, AzimuthFocus, ImageEntropy,
+                                            PhaseAdam, entropy_and_grad)
 from tests.gpu_util import announce, need_gpu, upload
 
 pytestmark = pytest.mark.gpu
@@ -133,3 +134,70 @@ def test_fused_image_entropy_matches_separate_passes(mode, with_phase, bpc):
     phi32 = phi.astype(np.float32).astype(np.float64) if with_phase else np.zeros(npul)
     E_ref, _ = oracle.autofocus(rcq, Haq, phi32)
     assert abs(st2[2] - E_ref) <= (1e-4 if mode == "fp32" else 2e-3) * abs(E_ref)
+
+
+@pytest.mark.parametrize("n", [1, 1000, 4096, 5000])
+def test_adam_step_matches_oracle(n):
+    # three consecutive steps with the moments and step count on the device
+    need_gpu()
+    announce(f"adam n={n}")
+    rng = np.random.default_rng(n)
+    phi0 = rng.standard_normal(n)
+    ph = torch.tensor(phi0, dtype=torch.float32, device="cuda")
+    opt = PhaseAdam(ph, lr=0.3)
+    phi, m, v = ph.cpu().numpy().astype(np.float64), np.zeros(n), np.zeros(n)
+    # the hyperparameters cross the C ABI as FP32: the oracle takes the same values
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
+    for k in range(1, 4):
+        g32 = (rng.standard_normal(n) * 10.0 ** rng.uniform(-3, 1, n)).astype(np.float32)
+        opt.step(torch.tensor(g32, device="cuda"))
+        phi, m, v = oracle.adam_step(phi, g32.astype(np.float64), m, v, k, f32(0.3), f32(0.9),
+                                     f32(0.999), f32(1e-8))
+        got = ph.cpu().numpy()
+        # FP32 arithmetic on values of order 1: a few ulps of each term
+        np.testing.assert_allclose(got, phi, rtol=0, atol=2e-6)
+    assert int(opt.count.item()) == 3
+
+
+def test_adam_rejects_bad_arguments():
+    need_gpu()
+    ph = torch.zeros(8, dtype=torch.float32, device="cuda")
+    opt = PhaseAdam(ph)
+    for kw in ({"lr": float("nan")}, {"betas": (1.0, 0.999)}, {"eps": 0.0}):
+        bad = PhaseAdam(ph, **kw)
+        with pytest.raises(_lib.BfpError):
+            bad.step(torch.zeros(8, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        opt.step(torch.zeros(7, dtype=torch.float32, device="cuda"))
+
+
+def test_autofocus_loop_graph_replays_equal_eager():
+    # the captured iteration (image + entropy, fused phase gradient, Adam)
+    # replayed step by step against the same iteration run eagerly on its own
+    # state, with synchronisations and eager work between the replays
+    need_gpu()
+    sc, rc_t, phi = _small_case(seed=8)
+    nr, npul = rc_t.shape
+    announce(f"autofocus loop graph vs eager nr={nr} npul={npul}")
+    rcd = upload(scenes.quantize(rc_t, "fp16"), "fp16")
+    Ha = api.filter_tensor(sc.azimuth_replica, npul, "fp16_fp32")
+    plan_g = AutofocusPlan(npul, nr, "fp16_fp32")
+    plan_e = AutofocusPlan(npul, nr, "fp16_fp32")
+    ph_g = torch.tensor(phi, dtype=torch.float32, device="cuda")
+    ph_e = ph_g.clone()
+    loop_g = AutofocusLoop(plan_g, rcd, Ha, ph_g, lr=0.1, graph=True)
+    loop_e = AutofocusLoop(plan_e, rcd, Ha, ph_e, lr=0.1, graph=False)
+    torch.cuda.synchronize()
+    E_first = None
+    for k in range(5):
+        loop_g.step()
+        torch.cuda.synchronize()
+        loop_e.step()
+        torch.cuda.synchronize()
+        assert torch.equal(ph_g, ph_e), f"step {k}"
+        assert torch.equal(loop_g.stats, loop_e.stats), f"step {k}"
+        if E_first is None:
+            E_first = float(loop_e.stats[2])
+    assert int(loop_g.opt.count.item()) == 5 and int(loop_e.opt.count.item()) == 5
+    # the steps descend the entropy
+    assert float(loop_e.entropy()) < E_first
