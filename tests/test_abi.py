@@ -53,6 +53,29 @@ def test_plan_validation_before_device_use():
     assert lib.fft_destroy(None) == _lib.EINVAL
 
 
+def test_adam_validation_before_launch():
+    # every argument is checked on the host before any launch; the pointers
+    # below are never dereferenced
+    lib = _lib.load()
+    p = ctypes.c_void_p(256)
+    ok = dict(n=8, lr=0.3, b1=0.9, b2=0.999, eps=1e-8)
+
+    def call(ptrs=(p, p, p, p, p), **kw):
+        a = dict(ok, **kw)
+        return lib.sar_autofocus_adam(*ptrs, a["n"], a["lr"], a["b1"], a["b2"], a["eps"], None)
+
+    assert call(ptrs=(None, p, p, p, p)) == _lib.EINVAL
+    assert call(ptrs=(p, p, p, p, None)) == _lib.EINVAL
+    assert call(n=0) == _lib.EINVAL
+    assert call(n=(1 << 20) + 1) == _lib.EINVAL
+    assert call(lr=float("nan")) == _lib.EINVAL
+    assert call(lr=-1.0) == _lib.EINVAL
+    assert call(b1=1.0) == _lib.EINVAL
+    assert call(b2=-0.1) == _lib.EINVAL
+    assert call(eps=0.0) == _lib.EINVAL
+    assert b"eps" in lib.bfp_last_error()
+
+
 @pytest.mark.parametrize("fmt", ["fp16", "fp32", "e4m3"])
 def test_host_filter_tables_match_oracle(fmt):
     # A1: FP64 host tables rounded once; compare with the oracle's filter
