@@ -138,6 +138,13 @@ def trace_summary(d, top=12):
     print("\n".join(out))
 
 
+def _finite_or_none(x, nd):
+    """Rounded float, or None where a collapsed image gives no finite figure
+    (the JSON line stays strict)."""
+    x = float(x)
+    return round(x, nd) if np.isfinite(x) else None
+
+
 def fft_flops(n, transforms):
     import math
     return 5.0 * n * math.log2(n) * transforms
@@ -735,7 +742,7 @@ def main():
                                                                          align=True), 2)
     if not args.quick:
         modes = {}
-        for mode in ("fp32", "fp16_fp32", "fp16_mul_fp32_acc", "e4m3"):
+        for mode in ("fp32", "fp16_fp32", "fp16_mul_fp32_acc", "e4m3", "e5m2"):
             log(f"range compression mode={mode}")
             r = bench_compress(mode, rows, n, args.steps, args.warmup)
             modes[mode] = {"gflops": round(r["gflops"], 1), "hbm_gbs": round(r["hbm_gbs"], 1),
@@ -769,21 +776,29 @@ def main():
         out["fft_n4096"] = fft
         from paper_2605_28451_amd import metrics as _m  # noqa: F401  (metrics of the GPU image only)
         sar = {}
-        for mode in ("fp16", "fp32", "fp16_fp32", "fp16_mul_fp32_acc"):
+        imgs = {}
+        for mode in ("fp16", "fp32", "fp16_fp32", "fp16_mul_fp32_acc", "e4m3", "e5m2"):
             log(f"SAR frame 4096x4096 mode={mode} (graph)")
             r = bench_sar_frame(mode, args.steps, args.warmup)
             sar[mode] = {k: (round(v, 4) if isinstance(v, float) else v)
                          for k, v in r.items() if not k.startswith("_")}
-            if mode == "fp16":
-                sar_fp16_img = r["_img"]
-                sc = r["_scene"]
-                pts = [_m.point_target(r["_img"], r0, a0, noise_patch=(r0 + 300, a0 + 300))
-                       for (r0, a0) in sc.targets]
-                sar["fp16_metrics"] = {
-                    "pslr_range_db_mean": round(float(np.mean([p["pslr_range"] for p in pts])), 3),
-                    "pslr_azimuth_db_mean": round(float(np.mean([p["pslr_azimuth"] for p in pts])), 3),
-                    "snr_db_mean": round(float(np.mean([p["snr"] for p in pts])), 2),
-                }
+            imgs[mode] = r["_img"]
+            sc = r["_scene"]
+            pts = [_m.point_target(r["_img"], r0, a0, noise_patch=(r0 + 300, a0 + 300))
+                   for (r0, a0) in sc.targets]
+            sar[mode]["image"] = {
+                k: _finite_or_none(np.mean([p[key] for p in pts]), nd)
+                for k, key, nd in (("pslr_range_db_mean", "pslr_range", 3),
+                                   ("pslr_azimuth_db_mean", "pslr_azimuth", 3),
+                                   ("snr_db_mean", "snr", 2))}
+        sar_fp16_img = imgs["fp16"]
+        sar["fp16_metrics"] = sar["fp16"]["image"]
+        # image SQNR of every mode against the FP32 path's image (real scale aligned)
+        for mode in imgs:
+            if mode != "fp32":
+                sar[mode]["image"]["sqnr_db_vs_fp32_path"] = _finite_or_none(
+                    _m.sqnr_db(imgs["fp32"], imgs[mode], align=True), 2)
+        del imgs
         log("SAR frame 4096x4096 mode=fp16, corner turn fused into the range store (graph)")
         r = bench_sar_frame("fp16", args.steps, args.warmup, fused_ct=True)
         sar["fp16_fused_corner_turn"] = {k: (round(v, 4) if isinstance(v, float) else v)
