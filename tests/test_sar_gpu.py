@@ -38,6 +38,32 @@ def test_range_compression_matches_oracle(mode):
         assert np.argmax(np.abs(rc[0, max(d - 3, 0):d + 4])) + max(d - 3, 0) == d
 
 
+def test_headline_compression_full_size_sampled_rows():
+    # the benchmark's workload and launch: 2048 pulses x 4096, pure FP16, the
+    # plan's default grid (the pipelined persistent kernel, 3 workgroups per
+    # CU); rows sampled across the grid's first, second and third iterations
+    need_gpu()
+    rows, n = 2048, 4096
+    announce(f"headline compression {rows}x{n} fp16, default grid, sampled rows")
+    sc = scenes.range_scene(seed=2, n_pulses=rows, n=n)
+    echo = scenes.quantize(sc.echo, "fp16")
+    plan = api.FFTPlan(n, rows, "fp16", flags=api.FLAG_CHECK_FINITE)
+    Hd = api.filter_tensor(sc.replica, n, "fp16")
+    rc = plan.range_compress(upload(echo, "fp16"), Hd)
+    assert plan.nonfinite() == 0
+    grid = 3 * torch.cuda.get_device_properties(0).multi_processor_count
+    pick = sorted({0, 1, 255, grid - 1, grid, grid + 1, 2 * grid - 1, 2 * grid, rows - 2, rows - 1})
+    got = download(rc[pick], "fp16")
+    H = scenes.quantize(oracle.matched_filter(sc.replica, n), "fp16")
+    ref = oracle.compress(echo[pick], H)
+    for i, r in enumerate(pick):
+        s = sqnr_db(ref[i], got[i], align=True)
+        assert s >= 52.0, (r, s)
+    s = sqnr_db(ref, got, align=True)
+    print(f"sampled rows {pick}: pooled SQNR {s:.2f} dB")
+    assert s >= 55.0
+
+
 @pytest.mark.parametrize("mode", ["fp32", "fp16", "fp16_fp32", "fp16_mul_fp32_acc"])
 @pytest.mark.parametrize("n", [256, 512, 1024, 2048, 4096, 8192, 16384])
 def test_compression_and_filtered_inverse_all_sizes(mode, n):
