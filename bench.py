@@ -653,6 +653,10 @@ def main():
                     help="profiling mode: run only the fused range-compression kernel of the "
                          "given precision (e.g. fp16) for --steps launches, then a plain device "
                          "copy of the same bytes (counter calibration); prints no JSON")
+    ap.add_argument("--section", default=None, choices=("sar_frame", "uneven", "autofocus"),
+                    help="profiling mode: run only one secondary workload (the 4096x4096 FP16 SAR "
+                         "frame graph, the 20,000-transform uneven batch, or the 4096x4096 "
+                         "autofocus loop) for --steps steps; prints its figures, no JSON line")
     ap.add_argument("--traffic-summary", nargs="+", metavar="MODE:FETCH_DIR:WRITE_DIR", default=None,
                     help="write the HBM traffic record from rocprofv3 --pmc runs of --kernel-only "
                          "(no GPU needed) and print its table")
@@ -688,6 +692,17 @@ def main():
         print(f"[kernel-only] device copy of {buf_in.numel()} B: {ms:.4f} ms, "
               f"{2 * buf_in.numel() / (ms * 1e-3) / 1e9:.0f} GB/s (read + write)",
               file=sys.stderr, flush=True)
+        return
+    if args.section:
+        if args.section == "sar_frame":
+            r = bench_sar_frame("fp16", args.steps, args.warmup)
+        elif args.section == "uneven":
+            r = bench_uneven("fp16", args.steps, args.warmup)
+        else:
+            r = bench_autofocus(args.steps)
+        print(f"[section] {args.section}: " + json.dumps(
+            {k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()
+             if not k.startswith("_")}), file=sys.stderr, flush=True)
         return
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
 
