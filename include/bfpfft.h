@@ -27,11 +27,12 @@
  *     last failure on the calling thread.
  *   - Plans are immutable after creation and may be used concurrently from
  *     several streams; a plan's non-finite counter is shared by all of them.
- *     Exception: a plan's phasor table and its entropy and autofocus
- *     workspaces are written by the calls that use them (an azimuth
- *     compression given a phase vector, sar_image_entropy,
- *     sar_azimuth_image_entropy, sar_azimuth_phase_grad); such calls must
- *     not overlap on one plan (give each stream its own plan for them).
+ *     Exception: a plan's phasor table, its entropy and autofocus
+ *     workspaces and an uneven plan's work-queue counter are written by
+ *     the calls that use them (an azimuth compression given a phase
+ *     vector, sar_image_entropy, sar_azimuth_image_entropy,
+ *     sar_azimuth_phase_grad, fft_exec_uneven); such calls must not overlap
+ *     on one plan (give each stream its own plan for them).
  */
 #ifndef BFPFFT_H
 #define BFPFFT_H
@@ -184,6 +185,10 @@ int fft_plan_uneven(bfp_plan *out, int count, const int *log2n,
 int fft_uneven_offsets(bfp_plan p, long long *offsets);
 /* Total complex elements of the packed buffer. */
 int fft_uneven_total(bfp_plan p, long long *total);
+/* One launch over the packed batch (in, out: device, fft_uneven_total
+ * complex elements in the plan's storage format); a one-thread kernel
+ * zeroes the plan's work-queue counter first, so calls on one plan must
+ * not overlap. */
 int fft_exec_uneven(bfp_plan p, const void *in, void *out, void *stream);
 
 /* ------------------------------------------------------------ tables --- */
