@@ -22,16 +22,23 @@ using bfp::RowArgs;
 namespace {
 
 // blocks_per_cu = kAutoBpc: the fused compression of pure FP16 up to n = 4096
-// runs the pipelined persistent kernel with 3 workgroups per CU (4 fit, by
-// LDS; at 2048 rows of 4096, 3, 5 and 8 measure alike and 4 and 6 slower);
-// every other operation one workgroup per row group (the single transforms
-// are faster at full occupancy).
+// runs the pipelined kernel on a grid of 3 workgroups per CU (4 fit, by
+// LDS; at 2048 rows of 4096, 3, 5 and 8 measure alike and 4 and 6 slower),
+// and of 8 per CU from 4096 rows of 4096 on (31.5 against 33.5 us at 4096
+// rows: the grid then outlasts one resident wave of workgroups), except for
+// the transposed store, whose XCD-aware row order wants the persistent grid
+// (a 4096 x 4096 frame with the fused corner turn: 156 us at 3, 166 us at
+// 8); every other operation one workgroup per row group (the single
+// transforms are faster at full occupancy).
 constexpr int kAutoBpc = -1;
 constexpr int kPipelinedBpc = 3;
+constexpr int kPipelinedBpcLarge = 8;
 
-int effective_bpc(const bfp_plan_s *p, int op) {
+int effective_bpc(const bfp_plan_s *p, int op, int rows, unsigned flags) {
   if (p->tune_bpc != kAutoBpc) return p->tune_bpc;
-  return (op == bfp::OP_COMPRESS && p->prec == BFP_FP16 && p->log2n <= 12) ? kPipelinedBpc : 0;
+  if (op != bfp::OP_COMPRESS || p->prec != BFP_FP16 || p->log2n > 12) return 0;
+  const bool transposed = ((flags | p->flags) & BFP_FLAG_TRANSPOSED_STORE) != 0;
+  return (p->log2n == 12 && rows >= 4096 && !transposed) ? kPipelinedBpcLarge : kPipelinedBpc;
 }
 
 
@@ -172,7 +179,7 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   a.phasor = phasor;
   a.flags = kflags(flags | p->flags);
   a.nonfinite = p->nonfinite;
-  const int bpc = effective_bpc(p, op);
+  const int bpc = effective_bpc(p, op, rows, flags);
   a.grid_limit = bpc > 0 ? bpc * p->cu_count : 0;
   a.engine = p->tune_engine;
   a.ent_partial = ent_partial;
