@@ -155,11 +155,18 @@ class AutofocusLoop:
         self.grad = torch.empty(n, dtype=torch.float32, device=rc_t.device)
         self.graph = None
         if graph:
-            # warm the launch path on a side stream, then capture one iteration
+            # one uncaptured pass of every kernel of the iteration on a side
+            # stream (its outputs are overwritten by every replay; the Adam
+            # launch goes to a throwaway state, so the optimiser's own state
+            # is untouched), then the capture of one iteration
             s = torch.cuda.Stream()
             s.wait_stream(torch.cuda.current_stream())
             g = torch.cuda.CUDAGraph()
             with torch.cuda.stream(s):
+                entropy_and_grad(plan, rc_t, h_az, phase, img=self.img, stats=self.stats,
+                                 grad=self.grad)
+                PhaseAdam(torch.zeros_like(phase), lr=lr).step(self.grad)
+                s.synchronize()
                 with torch.cuda.graph(g, stream=s):
                     self._iteration()
             torch.cuda.current_stream().wait_stream(s)
