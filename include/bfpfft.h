@@ -54,7 +54,7 @@ enum bfp_status {
 };
 
 /* ------------------------------------------------------ precision --- */
-/* Precision modes (paper Sec. V lists four; FP8 storage is Sec. VI).
+/* Precision modes (paper Sec. VI lists four; FP8 storage is Sec. VII).
  * "storage" = HBM element type; on-chip (LDS) intermediates between radix
  * passes are stored as noted; arithmetic as noted.                         */
 enum bfp_precision {
@@ -117,8 +117,13 @@ const char *bfp_last_error(void);
 int bfp_device_count(void);
 
 /* ------------------------------------------------------------ plans --- */
-/* Plan for `batch` independent transforms of length n = 2^k, 2^8..2^14, in
- * precision mode `prec`.  flags: BFP_FLAG_CHECK_FINITE, BFP_FLAG_OUT_FP32.
+/* Plan for `batch` independent transforms of length n = 2^k, 2^3..2^14, in
+ * precision mode `prec` (below 256 points a workgroup holds 256 * E / n
+ * transforms, E = 8 or 16 points per thread; n = 8 and 16 take one thread
+ * each).  flags: BFP_FLAG_CHECK_FINITE, BFP_FLAG_OUT_FP32,
+ * BFP_FLAG_CONJ_FILTER (every filtered call uses conj(filter); an azimuth
+ * compression's `adjoint` then reverts to the filter itself),
+ * BFP_FLAG_NAIVE_POSTSCALE, BFP_FLAG_AUTOFOCUS (n >= 256).
  * The plan owns its device twiddle tables (built on the host in FP64 with
  * exact argument reduction and rounded once, never by recurrence: Sec.
  * III-A) and its non-finite counter; it is bound to the device current at
@@ -146,8 +151,12 @@ int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *fi
                            unsigned flags, void *stream);
 
 /* Tuning knobs of a plan.  engine: 0 = matrix cores where the mode and size
- * have them (BFP_FP16_MUL_FP32_ACC at n = 4096), 1 = vector ALU only (the
- * default of a new plan: the faster engine on MI355X at every measured
+ * have them (BFP_FP16_MUL_FP32_ACC at n = 4096: forward, BFP inverse with
+ * or without a filter, and the compressions with a filter, its conjugate, a
+ * phase applied before the chain, FP32 output or the naive schedule; the
+ * output-phase adjoint, the transposed store, the adaptive shift and the
+ * migration correction always run on the vector ALU), 1 = vector ALU only
+ * (the default of a new plan: the faster engine on MI355X at every measured
  * size; fft_autotune may still select 0).
  * blocks_per_cu: rows plans: -1 = automatic (the default of a new plan:
  * the fused compression of pure FP16 at n <= 4096 uses k = 3, everything
@@ -280,9 +289,18 @@ int sar_corner_turn(const void *in, void *out, int rows, int cols, int fmt, void
  * laid out [range][pulse]: per range bin, the azimuth FFT, x H_a, the BFP
  * fold and the inverse.  phase: NULL, or (device) n_az FP32 radians; when
  * given, pulse m is first multiplied by exp(i phase[m]) (autofocus
- * correction).  adjoint != 0 applies the adjoint chain (conj(H_a) and
- * exp(-i phase[m]) applied after instead of before).  az_plan: n = pulses;
- * n_range <= plan batch rows are processed.  The image is [range][azimuth]. */
+ * correction).  adjoint != 0 applies the adjoint of that chain: with
+ * A(x) = IDFT(DFT(x e^{i phase}) H_a), A^H(y) = e^{-i phase} IDFT(DFT(y)
+ * conj(H_a)), i.e. the conjugated filter and exp(-i phase[m]) multiplied
+ * into the output instead of the input.  The filter used is conj(H_a) when
+ * exactly one of (BFP_FLAG_CONJ_FILTER in the call or the plan, adjoint)
+ * holds.  flags: BFP_FLAG_CHECK_FINITE, BFP_FLAG_CONJ_FILTER,
+ * BFP_FLAG_OUT_FP32 (with a phase only for the forward chain with H_a),
+ * BFP_FLAG_NAIVE_POSTSCALE (without a phase and without the conjugated
+ * filter); other combinations give BFP_EUNSUPPORTED before any launch.
+ * az_plan: n = pulses; n_range <= plan batch rows are processed.  The image
+ * is [range][azimuth]; the phase table is the plan's (calls with a phase
+ * must not overlap on one plan). */
 int sar_azimuth_compress(bfp_plan az_plan, const void *rc_t, void *image, const void *h_az,
                          const float *phase, int n_range, int adjoint, unsigned flags,
                          void *stream);

@@ -9,7 +9,7 @@ Two harnesses, both written from the text of the paper:
   then a +/- t) and a dual-select FMA butterfly (6 fused multiply-adds) that
   factors the larger of |cos|, |sin| out of the twiddle, following the
   fused-multiply-add FFT formulation of Linzer & Feig (1993).
-* ``storage_fft`` -- Sec. VI / Table V: FP64 arithmetic and twiddles, with
+* ``storage_fft`` -- Sec. VII / Table V: FP64 arithmetic and twiddles, with
   the data rounded to a storage format (FP16, OCP FP8 E4M3 or E5M2,
   saturating) after the input and after every radix-2 stage.
 

@@ -36,7 +36,7 @@ constexpr int kPipelinedBpcLarge = 8;
 
 int effective_bpc(const bfp_plan_s *p, int op, int rows, unsigned flags) {
   if (p->tune_bpc != kAutoBpc) return p->tune_bpc;
-  if (op != bfp::OP_COMPRESS || p->prec != BFP_FP16 || p->log2n > 12) return 0;
+  if (op != bfp::OP_COMPRESS || p->prec != BFP_FP16 || p->log2n > 12 || p->log2n < 8) return 0;
   const bool transposed = ((flags | p->flags) & BFP_FLAG_TRANSPOSED_STORE) != 0;
   return (p->log2n == 12 && rows >= 4096 && !transposed) ? kPipelinedBpcLarge : kPipelinedBpc;
 }
@@ -152,12 +152,20 @@ int check_rows_plan(bfp_plan p) {
   return BFP_OK;
 }
 
+// Private bits of run_rows' flags (outside the public bfp_flags): kExactConj
+// makes the call's BFP_FLAG_CONJ_FILTER bit authoritative (the plan's is not
+// ORed in: the adjoint of a conjugate-filter plan uses the filter itself);
+// kPostPhasor applies the phasor to the output (adjoint chains).
+constexpr unsigned kExactConj = 1u << 31;
+constexpr unsigned kPostPhasor = 1u << 30;
+
 unsigned kflags(unsigned f) {
   unsigned k = 0;
   if (f & BFP_FLAG_NAIVE_POSTSCALE) k |= bfp::KF_NAIVE;
   if (f & BFP_FLAG_CHECK_FINITE) k |= bfp::KF_CHECK_FINITE;
   if (f & BFP_FLAG_CONJ_FILTER) k |= bfp::KF_CONJ_FILTER;
   if (f & BFP_FLAG_TRANSPOSED_STORE) k |= bfp::KF_TRANSPOSED;
+  if (f & kPostPhasor) k |= bfp::KF_POST_PHASOR;
   return k;
 }
 
@@ -172,12 +180,12 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   a.in = in;
   a.out = out;
   a.rows = rows;
-  a.tw = p->tw;
-  if (bfp::has_mfma_engine(p->prec, p->log2n) && p->tune_engine == 1)
-    a.tw = static_cast<const unsigned char *>(p->tw) + bfp::kMfmaTableBytes;
+  a.tw = p->tw;  // the launcher picks the engine's part of a two-engine table
   a.filter = filter;
   a.phasor = phasor;
-  a.flags = kflags(flags | p->flags);
+  unsigned eff = flags | p->flags;
+  if (flags & kExactConj) eff = (eff & ~(unsigned)BFP_FLAG_CONJ_FILTER) | (flags & BFP_FLAG_CONJ_FILTER);
+  a.flags = kflags(eff);
   a.nonfinite = p->nonfinite;
   const int bpc = effective_bpc(p, op, rows, flags);
   a.grid_limit = bpc > 0 ? bpc * p->cu_count : 0;
@@ -188,7 +196,7 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   a.shift = shift;
   if (shift) a.flags |= bfp::KF_RAMP;
   if (grid_used) *grid_used = bfp::rows_grid(p->log2n, rows, a.grid_limit);
-  const bool out32 = ((flags | p->flags) & BFP_FLAG_OUT_FP32) != 0;
+  const bool out32 = (eff & BFP_FLAG_OUT_FP32) != 0;
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) return fail(BFP_EINVAL, "plan belongs to another device");
@@ -260,7 +268,7 @@ int fft_plan(bfp_plan *out, int n, int batch, int prec, unsigned flags) {
   if (!out) return fail(BFP_EINVAL, "out is NULL");
   *out = nullptr;
   const int l = log2_exact(n);
-  if (l < 8 || l > 14) return fail(BFP_EINVAL, "n must be a power of two in [256, 16384]");
+  if (l < 3 || l > 14) return fail(BFP_EINVAL, "n must be a power of two in [8, 16384]");
   if (batch < 0) return fail(BFP_EINVAL, "batch must be >= 0");
   if (!valid_prec(prec)) return fail(BFP_EINVAL, "unknown precision mode");
   if (flags & ~(unsigned)(BFP_FLAG_NAIVE_POSTSCALE | BFP_FLAG_CHECK_FINITE | BFP_FLAG_OUT_FP32 |
@@ -268,6 +276,8 @@ int fft_plan(bfp_plan *out, int n, int batch, int prec, unsigned flags) {
     return fail(BFP_EINVAL, "unknown plan flag");
   if ((flags & BFP_FLAG_AUTOFOCUS) && prec != BFP_FP32 && prec != BFP_FP16_STORE_FP32_COMPUTE)
     return fail(BFP_EINVAL, "autofocus plans need BFP_FP32 or BFP_FP16_STORE_FP32_COMPUTE");
+  if ((flags & BFP_FLAG_AUTOFOCUS) && l < 8)
+    return fail(BFP_EINVAL, "autofocus plans need n >= 256");
   int st = check_device();
   if (st) return st;
   bfp_plan p = new (std::nothrow) bfp_plan_s;
@@ -504,15 +514,24 @@ int sar_azimuth_compress(bfp_plan az_plan, const void *rc_t, void *image, const 
                           BFP_FLAG_OUT_FP32))
     return fail(BFP_EINVAL, "unknown flag for sar_azimuth_compress");
   if (rc_t == image) return fail(BFP_EINVAL, "rc_t and image must differ");
-  if (adjoint) {
-    if (phase) return fail(BFP_EUNSUPPORTED, "adjoint with phase: use the autofocus gradient");
-    flags ^= BFP_FLAG_CONJ_FILTER;
+  // the filter is conjugated when exactly one of (the call's or the plan's
+  // BFP_FLAG_CONJ_FILTER, adjoint) asks for it: the adjoint of the chain with
+  // conj(H) is the chain with H
+  const bool conj = (((flags | az_plan->flags) & BFP_FLAG_CONJ_FILTER) != 0) != (adjoint != 0);
+  if ((flags | az_plan->flags) & BFP_FLAG_NAIVE_POSTSCALE) {
+    if (conj || phase) return fail(BFP_EUNSUPPORTED, "BFP_FLAG_NAIVE_POSTSCALE combines with neither a phase nor the conjugated filter");
   }
+  if (phase && ((flags | az_plan->flags) & BFP_FLAG_OUT_FP32) && (conj || adjoint))
+    return fail(BFP_EUNSUPPORTED, "FP32 output with a phase vector is the forward chain with H only");
+  flags = (flags & ~(unsigned)BFP_FLAG_CONJ_FILTER) | (conj ? BFP_FLAG_CONJ_FILTER : 0u) | kExactConj;
   const void *ph = nullptr;
   if (phase) {
-    hipError_t e = bfp::launch_phasor(phase, az_plan->phasor, az_plan->n, 0, (hipStream_t)stream);
+    // forward: exp(+i phase) on the input; adjoint: exp(-i phase) on the output
+    hipError_t e = bfp::launch_phasor(phase, az_plan->phasor, az_plan->n, adjoint ? 1 : 0,
+                                      (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "phasor launch");
     ph = az_plan->phasor;
+    if (adjoint) flags |= kPostPhasor;
   }
   return run_rows(az_plan, bfp::OP_COMPRESS, rc_t, image, h_az, ph, n_range, flags, stream);
 }

@@ -69,6 +69,11 @@ static void geo(int &entries, int &passes, int *rad) {
 
 static void geometry(int log2n, int &entries, int &passes, int *rad) {
   switch (log2n) {
+    case 3: geo<3>(entries, passes, rad); return;
+    case 4: geo<4>(entries, passes, rad); return;
+    case 5: geo<5>(entries, passes, rad); return;
+    case 6: geo<6>(entries, passes, rad); return;
+    case 7: geo<7>(entries, passes, rad); return;
     case 8: geo<8>(entries, passes, rad); return;
     case 9: geo<9>(entries, passes, rad); return;
     case 10: geo<10>(entries, passes, rad); return;
@@ -100,6 +105,11 @@ int rows_grid(int log2n, int rows, int grid_limit) {
 
 int threads_per_transform(int log2n) {
   switch (log2n) {
+    case 3: return Geometry<3>::T;
+    case 4: return Geometry<4>::T;
+    case 5: return Geometry<5>::T;
+    case 6: return Geometry<6>::T;
+    case 7: return Geometry<7>::T;
     case 8: return Geometry<8>::T;
     case 9: return Geometry<9>::T;
     case 10: return Geometry<10>::T;

@@ -2,11 +2,14 @@
 // packed FP16, constant-twiddle radix-2/4/8/16 DFTs, storage conversions
 // (FP32, FP16, OCP FP8 E4M3/E5M2) and the precision-mode policies.
 //
-// Everything here is device code compiled for gfx950 only.  No device code
-// evaluates a sine or cosine: twiddles come from host-built FP64 tables
-// rounded once (the paper, Sec. III-A, ties the poor "42 dB" FP16 folklore
-// to recurrence-built tables), and the few radix constants below are exact
-// decimal expansions rounded by the compiler.
+// Everything here is device code compiled for gfx950 only.  No twiddle or
+// filter table is evaluated on the device: twiddles come from host-built FP64
+// tables rounded once (the paper, Sec. III-A, ties the poor "42 dB" FP16
+// folklore to recurrence-built tables), and the few radix constants below are
+// exact decimal expansions rounded by the compiler.  The only device
+// trigonometry is per row or per pulse, outside the transforms: the autofocus
+// phasor exp(i phi_m) (FP64 sincos, sar.hip) and the three migration phasors
+// per row of the RCMC compression (FP32 sincospif, rows.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -250,55 +253,36 @@ struct __attribute__((aligned(2))) fp8x2 {
   uint8_t x, y;
 };
 
-// OCP FP8 decode (exact).  E4M3: bias 7, 3 mantissa bits, 0x7F/0xFF NaN.
-// E5M2: bias 15, 2 mantissa bits, exponent 31 = inf/NaN.
-template <int MANT, int BIAS>
-__device__ __forceinline__ float fp8_decode(uint32_t b) {
-  uint32_t s = (b & 0x80u) << 24;
-  uint32_t e = (b >> MANT) & ((1u << (7 - MANT)) - 1u);
-  uint32_t m = b & ((1u << MANT) - 1u);
-  float v;
-  if (e == 0) {
-    v = (float)m * __builtin_bit_cast(float, (uint32_t)(127 + 1 - BIAS - MANT) << 23);
-  } else if (MANT == 3 && e == 15 && m == 7) {
-    v = __builtin_nanf("");
-  } else if (MANT == 2 && e == 31) {
-    v = m ? __builtin_nanf("") : __builtin_inff();
-  } else {
-    v = __builtin_bit_cast(float, ((e - BIAS + 127) << 23) | (m << (23 - MANT)));
+// OCP FP8 codec on gfx950's conversion instructions: v_cvt_pk_f32_fp8 /
+// v_cvt_pk_f32_bf8 decode two bytes exactly (E4M3: bias 7, 3 mantissa bits,
+// 0x7F/0xFF NaN; E5M2: bias 15, 2 mantissa bits, exponent 31 = inf/NaN), and
+// v_cvt_pk_fp8_f32 / v_cvt_pk_bf8_f32 round two FP32 values to nearest-even.
+// Saturation (|x| above the largest finite value maps to it, sign kept, NaN
+// stays NaN) is a compare and select ahead of the rounding: a comparison
+// with NaN is false, so NaN reaches the instruction, which keeps it NaN.
+// The codec is checked bit for bit against the host encoder over the whole
+// range, subnormals, saturation and NaN included.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <int MANT>
+struct Fp8Codec {
+  static_assert(MANT == 3 || MANT == 2, "E4M3 or E5M2");
+  static constexpr float kMax = MANT == 3 ? 448.0f : 57344.0f;
+  static __device__ __forceinline__ float sat(float x) {
+    return __builtin_fabsf(x) > kMax ? __builtin_copysignf(kMax, x) : x;
   }
-  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) | s);
-}
-
-// FP32 -> OCP FP8, round to nearest-even, saturating at the largest finite
-// value (NaN stays NaN).
-template <int MANT, int BIAS>
-__device__ __forceinline__ uint32_t fp8_encode(float x) {
-  uint32_t u = __builtin_bit_cast(uint32_t, x);
-  uint32_t s = (u >> 24) & 0x80u;
-  float a = __builtin_fabsf(x);
-  constexpr uint32_t emax_field = (MANT == 3) ? 15u : 30u;
-  constexpr uint32_t mmax = (MANT == 3) ? 6u : 3u;
-  // largest finite value: (1 + mmax / 2^MANT) * 2^(emax_field - BIAS)
-  const float maxv = __builtin_bit_cast(float, ((emax_field - BIAS + 127) << 23) | (mmax << (23 - MANT)));
-  if (!(a == a)) return s | 0x7Fu;  // NaN
-  if (a >= maxv) return s | (emax_field << MANT) | mmax;
-  const float min_normal = __builtin_bit_cast(float, (uint32_t)(127 + 1 - BIAS) << 23);
-  if (a < min_normal) {
-    // subnormal: multiple of 2^(1 - BIAS - MANT)
-    float q = __builtin_rintf(a * __builtin_bit_cast(float, (uint32_t)(127 - (1 - BIAS - MANT)) << 23));
-    return s | (uint32_t)q;  // q == 2^MANT rolls into the smallest normal
+  // bytes 0 and 1 of `bits` -> (x, y)
+  static __device__ __forceinline__ c32 decode2(uint32_t bits) {
+    f32x2 v;
+    if constexpr (MANT == 3) v = __builtin_amdgcn_cvt_pk_f32_fp8((int)bits, false);
+    else v = __builtin_amdgcn_cvt_pk_f32_bf8((int)bits, false);
+    return c32{v.x, v.y};
   }
-  uint32_t ua = __builtin_bit_cast(uint32_t, a);
-  constexpr int drop = 23 - MANT;
-  ua += ((1u << (drop - 1)) - 1u) + ((ua >> drop) & 1u);
-  ua &= ~((1u << drop) - 1u);
-  uint32_t e = (ua >> 23) - 127 + BIAS;
-  uint32_t m = (ua >> drop) & ((1u << MANT) - 1u);
-  uint32_t r = (e << MANT) | m;
-  uint32_t rmax = (emax_field << MANT) | mmax;
-  return s | (r > rmax ? rmax : r);
-}
+  // (x, y) -> bytes 0 and 1
+  static __device__ __forceinline__ uint32_t encode2(float x, float y) {
+    if constexpr (MANT == 3) return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(sat(x), sat(y), 0, false) & 0xFFFFu;
+    else return (uint32_t)__builtin_amdgcn_cvt_pk_bf8_f32(sat(x), sat(y), 0, false) & 0xFFFFu;
+  }
+};
 
 // ------------------------------------------------------ streaming I/O ---
 // Row data is read once and written once: nontemporal loads and stores keep
@@ -444,22 +428,20 @@ struct ModeF16MulF32Acc {
 template <int MANT, int BIAS>
 struct ModeFP8 {
   typedef fp8x2 Store; typedef c32 Lds; typedef c32 Comp; typedef c32 Tw; typedef c32 Filt;
+  typedef Fp8Codec<MANT> Codec;
   static __device__ __forceinline__ Comp decode(Store b) {
-    return c32{fp8_decode<MANT, BIAS>(b.x), fp8_decode<MANT, BIAS>(b.y)};
+    return Codec::decode2(__builtin_bit_cast(uint16_t, b));
   }
   static __device__ __forceinline__ Comp load(const Store *p, unsigned i) { return decode(ld_stream(p + i)); }
   static __device__ __forceinline__ Store encode(Comp v) {
-    return fp8x2{(uint8_t)fp8_encode<MANT, BIAS>(v.x), (uint8_t)fp8_encode<MANT, BIAS>(v.y)};
+    return __builtin_bit_cast(fp8x2, (uint16_t)Codec::encode2(v.x, v.y));
   }
   static __device__ __forceinline__ void store(Store *p, unsigned i, Comp v) { st_stream(p + i, encode(v)); }
   static __device__ __forceinline__ Lds to_lds(Comp v) { return v; }
   static __device__ __forceinline__ Comp from_lds(Lds v) { return v; }
   static __device__ __forceinline__ Comp twiddle(Lds v, Tw w) { return cmul(v, w); }
   static __device__ __forceinline__ Comp fmul(Comp v, Filt h) { return cmul(v, h); }
-  static __device__ __forceinline__ Comp round_store(Comp v) {
-    return c32{fp8_decode<MANT, BIAS>(fp8_encode<MANT, BIAS>(v.x)),
-               fp8_decode<MANT, BIAS>(fp8_encode<MANT, BIAS>(v.y))};
-  }
+  static __device__ __forceinline__ Comp round_store(Comp v) { return decode(encode(v)); }
 };
 typedef ModeFP8<3, 7> ModeE4M3;
 typedef ModeFP8<2, 15> ModeE5M2;

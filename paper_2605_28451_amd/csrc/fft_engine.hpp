@@ -23,8 +23,15 @@
 
 namespace bfp {
 
-// Radix plan per size: E values per thread, up to 4 passes.
+// Radix plan per size: E values per thread, up to 4 passes.  Below 256
+// points a transform takes 1 (N <= 16) to 8 threads and a workgroup holds
+// 256 / T transforms; N = 8 and 16 need no exchange at all.
 template <int LOG2N> struct Shape;
+template <> struct Shape<3>  { static constexpr int E = 8,  P = 1, R0 = 8,  R1 = 1,  R2 = 1, R3 = 1; };
+template <> struct Shape<4>  { static constexpr int E = 16, P = 1, R0 = 16, R1 = 1,  R2 = 1, R3 = 1; };
+template <> struct Shape<5>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 2,  R2 = 1, R3 = 1; };
+template <> struct Shape<6>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 4,  R2 = 1, R3 = 1; };
+template <> struct Shape<7>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 8,  R2 = 1, R3 = 1; };
 template <> struct Shape<8>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 16, R2 = 1, R3 = 1; };
 template <> struct Shape<9>  { static constexpr int E = 8,  P = 3, R0 = 8,  R1 = 8,  R2 = 8, R3 = 1; };
 template <> struct Shape<10> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 4, R3 = 1; };
@@ -42,9 +49,11 @@ template <> struct Shape<14> { static constexpr int E = 16, P = 4, R0 = 16, R1 =
 // span 8 at N = 512); after a span-256 pass the scatter is conflict-free
 // unpadded (C = 0).  N = 256 (four transforms per wavefront) keeps one pad
 // slot per 16.  One pad slot per 16 in every exchange made each read 2-way.
+// Below 256 points (at most 8 threads per transform) the single exchange is
+// unpadded.
 template <int LOG2N, int X>
 struct Pad {
-  static constexpr int C = LOG2N == 8 ? 1 : X == 0 ? 1 : X == 1 ? (LOG2N == 9 ? 8 : 4) : 0;
+  static constexpr int C = LOG2N < 8 ? 0 : LOG2N == 8 ? 1 : X == 0 ? 1 : X == 1 ? (LOG2N == 9 ? 8 : 4) : 0;
   static constexpr int S = LOG2N == 8 ? 4 : X == 0 ? 5 : 6;
   static __host__ __device__ constexpr int at(int i) { return i + C * (i >> S); }
 };

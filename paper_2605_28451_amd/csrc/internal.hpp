@@ -18,15 +18,18 @@ enum KFlags : unsigned {
   KF_CONJ_FILTER = 16u,  // multiply by conj(filter)
   KF_ADAPT = 32u,        // per-row adaptive block shift (row_exp)
   KF_RAMP = 64u,         // compression: per-row range shift (shift)
+  KF_POST_PHASOR = 128u, // compression: multiply the output (not the input) by the phasor
 };
 
 struct RowArgs {
   const void *in;
   void *out;
   int rows;
-  const void *tw;        // plan twiddle table (mode's twiddle type)
+  const void *tw;        // plan twiddle table (mode's twiddle type; with a matrix-core
+                         // engine its operands first, the vector table at kMfmaTableBytes)
   const void *filter;    // n elements or NULL
-  const void *phasor;    // n FP32 pairs exp(i phi_m) or NULL (compress only)
+  const void *phasor;    // n FP32 pairs exp(+-i phi_m) or NULL (compress only): applied
+                         // to the input, or to the output with KF_POST_PHASOR
   unsigned flags;        // KFlags
   unsigned long long *nonfinite;  // device counter
   int grid_limit;        // > 0: persistent grid of at most this many workgroups

@@ -47,9 +47,12 @@ __device__ __forceinline__ h2 mul_c32(h2 v, c32 p) { return cmul(v, c32_to_h2(p)
 
 // Compile-time variants of the inverse / compression kernels (no runtime
 // selects in the per-element code): conventional post-scaling (debug),
-// conjugated filter (adjoint), per-pulse phasor at load.
+// conjugated filter (adjoint), per-pulse phasor at load, or, with V_POST,
+// applied to the output instead (the adjoint of a phase-corrected
+// compression: A = C diag(e^{i phi}) has A^H = diag(e^{-i phi}) C^H, and C^H
+// is the same chain with the conjugated filter).
 enum Variant { V_PLAIN = 0, V_NAIVE = 1, V_CONJ = 2, V_PHASOR = 4, V_TRANS = 8, V_ENT = 16,
-               V_ADAPT = 32, V_RAMP = 64 };
+               V_ADAPT = 32, V_RAMP = 64, V_POST = 128 };
 
 // Range cell migration correction folded into the range compression (the
 // RCMC step of the range-Doppler pipeline, Sec. VI): row r (one Doppler
@@ -124,6 +127,9 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   constexpr bool naive = (V & V_NAIVE) != 0;
   constexpr bool conj_f = (V & V_CONJ) != 0;
   constexpr bool phasor = (V & V_PHASOR) != 0;
+  constexpr bool post = (V & V_POST) != 0;
+  static_assert(!post || (phasor && OP == OP_COMPRESS && (V & ~(V_PHASOR | V_POST | V_CONJ)) == 0),
+                "the output phasor is a variant of the (conjugate-filter) compression");
   constexpr bool trans = (V & V_TRANS) != 0;
   static_assert(!trans || (OP == OP_COMPRESS && V == V_TRANS && !OUT32),
                 "the transposed store is a variant of the plain compression");
@@ -246,7 +252,7 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = Comp{};
   }
-  if constexpr (OP == OP_COMPRESS && phasor) {
+  if constexpr (OP == OP_COMPRESS && phasor && !post) {
     if (active) {
       const c32 *ph = static_cast<const c32 *>(a.phasor) + tt;
 #pragma unroll
@@ -328,6 +334,13 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
       for (int e = 0; e < E; ++e) v[e] = pow2<LOG2N>(M::round_store(cconj(v[e])));
     } else {
       transform_conj(v, tt);
+    }
+  }
+  if constexpr (post) {
+    if (active) {
+      const c32 *ph = static_cast<const c32 *>(a.phasor) + tt;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = mul_c32(v[e], ph[T * e]);
     }
   }
 
@@ -519,14 +532,8 @@ static hipError_t launch_mfma(const RowArgs &a, hipStream_t s) {
 #endif
 
 template <int LOG2N, int OP, int V, bool OUT32>
-static hipError_t launch_one(const RowArgs &a, hipStream_t s) {
+static hipError_t launch_vector(const RowArgs &a, hipStream_t s) {
   typedef Geometry<LOG2N> G;
-  if (a.rows <= 0) return hipSuccess;
-#if BFP_MODE_ID == 3
-  if constexpr (LOG2N == 12 && (V & (V_TRANS | V_ADAPT | V_RAMP)) == 0) {
-    if (a.engine == 0) return launch_mfma<OP, V, OUT32>(a, s);
-  }
-#endif
   unsigned grid = (unsigned)((a.rows + G::TPW - 1) / G::TPW);
   if (a.grid_limit > 0 && grid > (unsigned)a.grid_limit) grid = (unsigned)a.grid_limit;
   if constexpr (Engine<MODE, LOG2N>::kTwRegs) {
@@ -539,6 +546,26 @@ static hipError_t launch_one(const RowArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// a.tw is the plan's table.  Where a matrix-core engine exists, that table
+// starts with the matrix-core operands and the vector engine's twiddles
+// follow at kMfmaTableBytes: variants without a matrix-core kernel run on
+// the vector engine whatever the plan's engine, with its table.
+template <int LOG2N, int OP, int V, bool OUT32>
+static hipError_t launch_one(const RowArgs &a, hipStream_t s) {
+  if (a.rows <= 0) return hipSuccess;
+#if BFP_MODE_ID == 3
+  if constexpr (LOG2N == 12) {
+    if constexpr ((V & (V_TRANS | V_ADAPT | V_RAMP | V_POST)) == 0) {
+      if (a.engine == 0) return launch_mfma<OP, V, OUT32>(a, s);
+    }
+    RowArgs b = a;
+    b.tw = static_cast<const unsigned char *>(a.tw) + kMfmaTableBytes;
+    return launch_vector<LOG2N, OP, V, OUT32>(b, s);
+  }
+#endif
+  return launch_vector<LOG2N, OP, V, OUT32>(a, s);
+}
+
 // Variant selection; combinations outside this table are rejected by the
 // C layer before launch.
 template <int LOG2N>
@@ -546,6 +573,7 @@ static hipError_t launch_size(int op, bool out32, const RowArgs &a, hipStream_t 
   const bool naive = (a.flags & KF_NAIVE) != 0;
   const bool conj = (a.flags & KF_CONJ_FILTER) != 0;
   const bool ph = a.phasor != nullptr;
+  const bool post = (a.flags & KF_POST_PHASOR) != 0;
   switch (op) {
     case OP_FWD:
       return out32 ? launch_one<LOG2N, OP_FWD, V_PLAIN, true>(a, s)
@@ -583,11 +611,11 @@ static hipError_t launch_size(int op, bool out32, const RowArgs &a, hipStream_t 
         if (naive || conj || ph || out32) return hipErrorInvalidValue;
         return launch_one<LOG2N, OP_COMPRESS, V_TRANS, false>(a, s);
       }
-      if ((naive && (conj || ph)) || (conj && ph)) return hipErrorInvalidValue;
+      if (post && !ph) return hipErrorInvalidValue;
+      if (naive && (conj || ph)) return hipErrorInvalidValue;
       if (naive) return out32 ? hipErrorInvalidValue : launch_one<LOG2N, OP_COMPRESS, V_NAIVE, false>(a, s);
-      if (conj) return out32 ? hipErrorInvalidValue : launch_one<LOG2N, OP_COMPRESS, V_CONJ, false>(a, s);
       if (a.ent_partial) {
-        if (!out32 || naive || conj) return hipErrorInvalidValue;
+        if (!out32 || conj || post) return hipErrorInvalidValue;
 #if BFP_MODE_ID == 0 || BFP_MODE_ID == 2
         return ph ? launch_one<LOG2N, OP_COMPRESS, V_PHASOR | V_ENT, true>(a, s)
                   : launch_one<LOG2N, OP_COMPRESS, V_ENT, true>(a, s);
@@ -595,6 +623,15 @@ static hipError_t launch_size(int op, bool out32, const RowArgs &a, hipStream_t 
         return hipErrorInvalidValue;
 #endif
       }
+      if (ph && (conj || post)) {
+        // phase-corrected compression with the conjugated filter, and the
+        // adjoints (output phasor) of both filter choices
+        if (out32) return hipErrorInvalidValue;
+        if (!post) return launch_one<LOG2N, OP_COMPRESS, V_PHASOR | V_CONJ, false>(a, s);
+        return conj ? launch_one<LOG2N, OP_COMPRESS, V_PHASOR | V_POST | V_CONJ, false>(a, s)
+                    : launch_one<LOG2N, OP_COMPRESS, V_PHASOR | V_POST, false>(a, s);
+      }
+      if (conj) return out32 ? hipErrorInvalidValue : launch_one<LOG2N, OP_COMPRESS, V_CONJ, false>(a, s);
       if (ph)
         return out32 ? launch_one<LOG2N, OP_COMPRESS, V_PHASOR, true>(a, s)
                      : launch_one<LOG2N, OP_COMPRESS, V_PHASOR, false>(a, s);
@@ -610,6 +647,11 @@ static hipError_t launch_size(int op, bool out32, const RowArgs &a, hipStream_t 
 hipError_t BFP_CAT(launch_rows_mode, BFP_MODE_ID)(int log2n, int op, bool out32, const RowArgs &a,
                                                  hipStream_t s) {
   switch (log2n) {
+    case 3: return launch_size<3>(op, out32, a, s);
+    case 4: return launch_size<4>(op, out32, a, s);
+    case 5: return launch_size<5>(op, out32, a, s);
+    case 6: return launch_size<6>(op, out32, a, s);
+    case 7: return launch_size<7>(op, out32, a, s);
     case 8: return launch_size<8>(op, out32, a, s);
     case 9: return launch_size<9>(op, out32, a, s);
     case 10: return launch_size<10>(op, out32, a, s);

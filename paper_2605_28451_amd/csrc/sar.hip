@@ -123,14 +123,8 @@ __device__ __forceinline__ c32 load_fmt(const void *p, long long i, int fmt) {
   switch (fmt) {
     case 0: return static_cast<const c32 *>(p)[i];
     case 1: return h2_to_c32(static_cast<const h2 *>(p)[i]);
-    case 2: {
-      fp8x2 b = static_cast<const fp8x2 *>(p)[i];
-      return c32{fp8_decode<3, 7>(b.x), fp8_decode<3, 7>(b.y)};
-    }
-    default: {
-      fp8x2 b = static_cast<const fp8x2 *>(p)[i];
-      return c32{fp8_decode<2, 15>(b.x), fp8_decode<2, 15>(b.y)};
-    }
+    case 2: return Fp8Codec<3>::decode2(static_cast<const uint16_t *>(p)[i]);
+    default: return Fp8Codec<2>::decode2(static_cast<const uint16_t *>(p)[i]);
   }
 }
 
@@ -140,13 +134,8 @@ __device__ __forceinline__ void store_fmt(void *p, long long i, int fmt, c32 v) 
   switch (fmt) {
     case 0: static_cast<c32 *>(p)[i] = v; break;
     case 1: static_cast<h2 *>(p)[i] = c32_to_h2(v); break;
-    case 2:
-      static_cast<fp8x2 *>(p)[i] = fp8x2{(uint8_t)fp8_encode<3, 7>(v.x), (uint8_t)fp8_encode<3, 7>(v.y)};
-      break;
-    default:
-      static_cast<fp8x2 *>(p)[i] =
-          fp8x2{(uint8_t)fp8_encode<2, 15>(v.x), (uint8_t)fp8_encode<2, 15>(v.y)};
-      break;
+    case 2: static_cast<uint16_t *>(p)[i] = (uint16_t)Fp8Codec<3>::encode2(v.x, v.y); break;
+    default: static_cast<uint16_t *>(p)[i] = (uint16_t)Fp8Codec<2>::encode2(v.x, v.y); break;
   }
 }
 

@@ -6,7 +6,7 @@
   exponent relative to an unscaled reference); ``align=False`` uses a = 1.
 * ``point_target`` -- PSLR, ISLR, 3 dB impulse-response width (IRW) and SNR
   of one point target, measured in range and in azimuth.  The paper does not
-  state its procedure (Sec. V); the one used here is: take a 64x64 chip
+  state its procedure (Sec. VI); the one used here is: take a 64x64 chip
   centred on the peak, upsample it x16 by FFT zero-padding (FP64), cut through
   the upsampled peak along each axis, delimit the mainlobe by the first local
   minimum on each side, then

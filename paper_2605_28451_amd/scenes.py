@@ -3,7 +3,7 @@
 This module holds no arithmetic of the transform or of matched filtering: it
 draws random numbers, synthesises radar echoes (replicas placed at target
 positions plus noise) and encodes values into the storage formats.  The
-paper's scene (Sec. V: X-band, B = 100 MHz, v = 100 m/s, R0 = 20 km, 20 dB
+paper's scene (Sec. VI: X-band, B = 100 MHz, v = 100 m/s, R0 = 20 km, 20 dB
 additive noise) is not fully specified, so the workloads are stated in
 normalised units:
 

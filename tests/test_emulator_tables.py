@@ -2,7 +2,7 @@
 
 These pins fix the SQNR definition (pooled energy, FP64 reference on the
 unquantised draw) and the rounding model that the GPU numbers are compared
-under.  Printed values: Table I (Sec. III-A) and Table V (Sec. VI); the
+under.  Printed values: Table I (Sec. III-A) and Table V (Sec. VII); the
 fixtures live in tests/golden/ with their citations.
 """
 import json

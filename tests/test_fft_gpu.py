@@ -12,8 +12,8 @@ import torch
 import oracle
 from paper_2605_28451_amd.metrics import sqnr_db
 from paper_2605_28451_amd import api, scenes
-from tests.gpu_util import (FP16_MODES, FWD_SQNR_MIN, MODES, announce, download, need_gpu,
-                            rand_rows, upload)
+from tests.gpu_util import (FP16_MODES, FWD_SQNR_MIN, MODES, ROUNDTRIP_SQNR_MIN, announce, download,
+                            need_gpu, rand_rows, upload)
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def test_forward_n4096_sqnr(mode):
     X = download(plan.forward(upload(x, fmt)), fmt)
     ref = oracle.fft(x)
     s = sqnr_db(ref, X)
-    print(f"mode={mode} forward SQNR {s:.2f} dB")
+    print(f"[measure] forward_n4096.{mode} {s:.3f}")
     assert np.all(np.isfinite(X))
     assert s >= FWD_SQNR_MIN[mode]
 
@@ -51,13 +51,16 @@ def test_forward_and_inverse_all_sizes(mode, n):
     plan = api.FFTPlan(n, rows, mode)
     X = download(plan.forward(upload(x, fmt)), fmt)
     s = sqnr_db(oracle.fft(x), X)
-    bar = FWD_SQNR_MIN[mode] - (3.0 if n > 4096 else 0.0)
+    print(f"[measure] forward_all_sizes.{mode}.n{n} {s:.3f}")
+    # one more radix pass above 4096 points
+    bar = FWD_SQNR_MIN[mode] - (1.5 if n > 4096 else 0.0)
     assert s >= bar, (n, mode, s)
     # BFP inverse of a fresh spectrum-domain input (normalised IDFT)
     z = scenes.quantize(rand_rows(rows, n, n + 8) * np.sqrt(n), fmt)
     y = download(plan.inverse_bfp(upload(z, fmt)), fmt)
     si = sqnr_db(oracle.fft(z, inverse=True), y)
-    assert si >= bar - 3.0, (n, mode, si)
+    print(f"[measure] inverse_all_sizes.{mode}.n{n} {si:.3f}")
+    assert si >= bar, (n, mode, si)
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -71,8 +74,8 @@ def test_round_trip_config1(mode):
     X = plan.forward(upload(x, fmt))
     y = download(plan.inverse_bfp(X), fmt)
     s = sqnr_db(x, y)
-    print(f"mode={mode} round-trip SQNR {s:.2f} dB")
-    assert s >= FWD_SQNR_MIN[mode] - 3.0
+    print(f"[measure] round_trip.{mode} {s:.3f}")
+    assert s >= ROUNDTRIP_SQNR_MIN[mode]
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -184,6 +187,8 @@ def test_invalid_arguments_rejected():
     need_gpu()
     with pytest.raises(api._lib.BfpError):
         api.FFTPlan(1000, 1, "fp16")
+    with pytest.raises(api._lib.BfpError):
+        api.FFTPlan(4, 1, "fp16")
     with pytest.raises(api._lib.BfpError):
         api.FFTPlan(32768, 1, "fp16")
     with pytest.raises(api._lib.BfpError):

@@ -11,8 +11,11 @@ from tests.gpu_util import announce, download, need_gpu, upload
 
 pytestmark = pytest.mark.gpu
 
-RC_SQNR_MIN = {"fp32": 120.0, "fp16": 45.0, "fp16_fp32": 50.0, "fp16_mul_fp32_acc": 50.0,
-               "e4m3": 12.0, "e5m2": 6.0}
+# unaligned compression SQNR bars (dB), about 3 dB under the lowest value
+# measured over N = 256..16384 (FP32 134.4, pure FP16 56.8, FP16 storage
+# 65.6, FP16 multiply 63.5; E4M3 38.8 and E5M2 29.8 on the range scene)
+RC_SQNR_MIN = {"fp32": 131.0, "fp16": 53.8, "fp16_fp32": 62.5, "fp16_mul_fp32_acc": 60.5,
+               "e4m3": 35.5, "e5m2": 26.5}
 
 
 @pytest.mark.parametrize("mode", ["fp32", "fp16", "fp16_fp32", "fp16_mul_fp32_acc", "e4m3", "e5m2"])
@@ -30,37 +33,36 @@ def test_range_compression_matches_oracle(mode):
     Hd = api.filter_tensor(sc.replica, 4096, mode)
     rc = download(plan.range_compress(upload(echo, fmt), Hd), fmt)
     assert plan.nonfinite() == 0
-    s = sqnr_db(ref, rc, align=True)
-    print(f"mode={mode} range-compression SQNR {s:.2f} dB")
+    s = sqnr_db(ref, rc)
+    print(f"[measure] range_compression.{mode} {s:.3f}")
     assert s >= RC_SQNR_MIN[mode]
     # peaks at the target delays
     for d in sc.delays:
         assert np.argmax(np.abs(rc[0, max(d - 3, 0):d + 4])) + max(d - 3, 0) == d
 
 
-def test_headline_compression_full_size_sampled_rows():
+def test_headline_compression_full_size_every_row():
     # the benchmark's workload and launch: 2048 pulses x 4096, pure FP16, the
-    # plan's default grid (the pipelined persistent kernel, 3 workgroups per
-    # CU); rows sampled across the grid's first, second and third iterations
+    # plan's default grid (the pipelined persistent kernel); every row
+    # against the oracle, unaligned (the BFP inverse must equal the
+    # normalised inverse)
     need_gpu()
     rows, n = 2048, 4096
-    announce(f"headline compression {rows}x{n} fp16, default grid, sampled rows")
+    announce(f"headline compression {rows}x{n} fp16, default grid, every row")
     sc = scenes.range_scene(seed=2, n_pulses=rows, n=n)
     echo = scenes.quantize(sc.echo, "fp16")
     plan = api.FFTPlan(n, rows, "fp16", flags=api.FLAG_CHECK_FINITE)
     Hd = api.filter_tensor(sc.replica, n, "fp16")
-    rc = plan.range_compress(upload(echo, "fp16"), Hd)
+    got = download(plan.range_compress(upload(echo, "fp16"), Hd), "fp16")
     assert plan.nonfinite() == 0
-    grid = 3 * torch.cuda.get_device_properties(0).multi_processor_count
-    pick = sorted({0, 1, 255, grid - 1, grid, grid + 1, 2 * grid - 1, 2 * grid, rows - 2, rows - 1})
-    got = download(rc[pick], "fp16")
     H = scenes.quantize(oracle.matched_filter(sc.replica, n), "fp16")
-    ref = oracle.compress(echo[pick], H)
-    for i, r in enumerate(pick):
-        s = sqnr_db(ref[i], got[i], align=True)
-        assert s >= 52.0, (r, s)
-    s = sqnr_db(ref, got, align=True)
-    print(f"sampled rows {pick}: pooled SQNR {s:.2f} dB")
+    ref = oracle.compress(echo, H)
+    per_row = 10.0 * np.log10(np.sum(np.abs(ref) ** 2, 1) / np.sum(np.abs(ref - got) ** 2, 1))
+    s = sqnr_db(ref, got)
+    print(f"[measure] headline_rows_min {per_row.min():.3f}")
+    print(f"[measure] headline_pooled {s:.3f}")
+    # measured: worst row 56.5 dB, pooled 57.4 dB
+    assert per_row.min() >= 53.5, (int(np.argmin(per_row)), per_row.min())
     assert s >= 55.0
 
 
@@ -81,9 +83,10 @@ def test_compression_and_filtered_inverse_all_sizes(mode, n):
     H = scenes.quantize(oracle.matched_filter(sc.replica, n), ffmt)
     plan = api.FFTPlan(n, rows, mode, flags=api.FLAG_CHECK_FINITE)
     Hd = api.filter_tensor(sc.replica, n, mode)
-    bar = RC_SQNR_MIN[mode] - (3.0 if n > 4096 else 0.0)
+    bar = RC_SQNR_MIN[mode]
     rc = download(plan.range_compress(upload(echo, fmt), Hd), fmt)
-    s = sqnr_db(oracle.compress(echo, H), rc, align=True)
+    s = sqnr_db(oracle.compress(echo, H), rc)
+    print(f"[measure] compression_all_sizes.{mode}.n{n} {s:.3f}")
     assert s >= bar, (n, mode, s)
     # every target is a peak of its neighbourhood (equal amplitudes: no global order)
     for d in sc.delays:
@@ -93,7 +96,8 @@ def test_compression_and_filtered_inverse_all_sizes(mode, n):
     g = np.random.default_rng(n + 9).standard_normal((2, rows, n))
     z = scenes.quantize((g[0] + 1j * g[1]) * np.sqrt(n), fmt)
     y = download(plan.inverse_bfp(upload(z, fmt), Hd), fmt)
-    si = sqnr_db(oracle.fft(z * H, inverse=True), y, align=True)
+    si = sqnr_db(oracle.fft(z * H, inverse=True), y)
+    print(f"[measure] filtered_inverse_all_sizes.{mode}.n{n} {si:.3f}")
     assert si >= bar, (n, mode, si)
     assert plan.nonfinite() == 0
 
@@ -223,8 +227,21 @@ def _oracle_frame(sc, mode, phase=None):
     return oracle.sar_image(scenes.quantize(sc.echo, fmt), Hr, Ha, phi=phase)
 
 
-FRAME_SQNR_MIN = {"fp16": 40.0, "fp16_fp32": 45.0, "fp16_mul_fp32_acc": 45.0, "fp32": 110.0,
-                  "e4m3": 10.0, "e5m2": 5.0}
+# frame SQNR bars (dB), about 3 dB under the measured values (pure FP16 55.4,
+# FP16 storage 64.0, FP16 multiply 62.5, FP32 132.7, E4M3 29.3, E5M2 23.8);
+# pure FP16 also meets the 40 dB end-to-end bar
+FRAME_SQNR_MIN = {"fp16": 52.5, "fp16_fp32": 61.0, "fp16_mul_fp32_acc": 59.5, "fp32": 129.5,
+                  "e4m3": 26.5, "e5m2": 21.0}
+# (PSLR/ISLR dB, SNR dB, IRW samples) bars of the frame metrics against the
+# oracle: the paper's 0.1 dB / 0.02-bin parity for the FP16 and FP32 modes
+# (worst measured over the 9 targets: 0.007 dB, 0.0003 samples).  The FP8
+# storage modes are the paper's FP8 study (Sec. VII) carried to the image:
+# worst measured E4M3 PSLR 0.17 / ISLR 0.10 / SNR 0.23 dB / IRW 0.005, E5M2
+# 0.52 / 0.46 / 0.42 dB / 0.021; their bars are 0.5 / 1.0 dB (PSLR, ISLR,
+# SNR) and 0.02 / 0.05 samples
+FRAME_METRIC_BARS = {"fp16": (0.1, 0.1, 0.02), "fp16_fp32": (0.1, 0.1, 0.02),
+                     "fp16_mul_fp32_acc": (0.1, 0.1, 0.02), "fp32": (0.1, 0.1, 0.02),
+                     "e4m3": (0.5, 0.5, 0.02), "e5m2": (1.0, 1.0, 0.05)}
 
 
 @pytest.mark.parametrize("mode", ["fp16", "fp16_fp32", "fp16_mul_fp32_acc", "fp32", "e4m3", "e5m2"])
@@ -235,20 +252,30 @@ def test_sar_frame_4096_matches_oracle_metrics(mode):
     sc = scenes.sar_scene(seed=3)
     img = _gpu_frame(sc, mode)
     ref = _oracle_frame(sc, mode)
-    s = metrics.sqnr_db(ref, img, align=True)
-    print(f"mode={mode} frame SQNR {s:.2f} dB")
+    s = metrics.sqnr_db(ref, img)
+    print(f"[measure] frame_sqnr.{mode} {s:.3f}")
     assert np.all(np.isfinite(img))
     assert s >= FRAME_SQNR_MIN[mode]
-    if mode in ("e4m3", "e5m2"):
-        return
+    # FP8 storage rounds the echo, the range-compressed data and the image
+    # to 3 (E4M3) or 2 (E5M2) mantissa bits; the oracle sees only the rounded
+    # echo, so the image metrics move further than in the FP16 modes: their
+    # bars are readings of the FP8 floor (PSLR/ISLR, SNR, IRW per mode)
+    bar_db, bar_snr, bar_irw = FRAME_METRIC_BARS[mode]
+    worst = {}
     for (r0, a0) in sc.targets:
         mg = metrics.point_target(img, r0, a0, noise_patch=(r0 + 300, a0 + 300))
         mo = metrics.point_target(ref, r0, a0, noise_patch=(r0 + 300, a0 + 300))
         assert mg["peak_rc"] == mo["peak_rc"] == (r0, a0)
-        for k in ("pslr_range", "pslr_azimuth", "islr_range", "islr_azimuth", "snr"):
-            assert abs(mg[k] - mo[k]) <= 0.1, (r0, a0, k, mg[k], mo[k])
+        for k in ("pslr_range", "pslr_azimuth", "islr_range", "islr_azimuth", "snr",
+                  "irw_range", "irw_azimuth"):
+            worst[k] = max(worst.get(k, 0.0), abs(mg[k] - mo[k]))
+        for k in ("pslr_range", "pslr_azimuth", "islr_range", "islr_azimuth"):
+            assert abs(mg[k] - mo[k]) <= bar_db, (r0, a0, k, mg[k], mo[k])
+        assert abs(mg["snr"] - mo["snr"]) <= bar_snr, (r0, a0, mg["snr"], mo["snr"])
         for k in ("irw_range", "irw_azimuth"):
-            assert abs(mg[k] - mo[k]) <= 0.02, (r0, a0, k, mg[k], mo[k])
+            assert abs(mg[k] - mo[k]) <= bar_irw, (r0, a0, k, mg[k], mo[k])
+    for k, v in worst.items():
+        print(f"[measure] frame_worst_delta.{mode}.{k} {v:.4f}")
 
 
 def _weighted_frames(sc, mode, taper):
@@ -316,12 +343,16 @@ def test_azimuth_phase_correction_matches_oracle():
     phi = rng.uniform(-3, 3, 1024).astype(np.float32).astype(np.float64)
     img = _gpu_frame(sc, "fp16_fp32", phase=phi)
     ref = _oracle_frame(sc, "fp16_fp32", phase=phi)
-    assert metrics.sqnr_db(ref, img, align=True) >= 45.0
+    s = metrics.sqnr_db(ref, img)
+    print(f"[measure] phase_corrected_frame.fp16_fp32 {s:.3f}")
+    assert s >= 60.5  # measured 63.7
 
 
 # ------------------------------------------ range cell migration (RCMC) ----
-RCMC_SQNR_MIN = {"fp32": 110.0, "fp16_fp32": 60.0, "fp16_mul_fp32_acc": 58.0, "fp16": 52.0,
-                 "e4m3": 12.0, "e5m2": 8.0}
+# measured at N = 4096 / 1024: FP32 130.7 / 131.2, FP16 storage 66.0, FP16
+# multiply 64.1 / 64.2, pure FP16 57.2 / 58.1, E4M3 31.5
+RCMC_SQNR_MIN = {"fp32": 127.5, "fp16_fp32": 63.0, "fp16_mul_fp32_acc": 61.0, "fp16": 54.0,
+                 "e4m3": 28.5, "e5m2": 22.0}
 
 
 @pytest.mark.parametrize("mode", ["fp32", "fp16_fp32", "fp16_mul_fp32_acc", "fp16", "e4m3"])
@@ -344,7 +375,7 @@ def test_rcmc_compress_matches_oracle(mode, n, rows):
     got = download(y, fmt)
     ref = oracle.rcmc_compress(x, Hq, shift.astype(np.float64))
     s = metrics.sqnr_db(ref, got)
-    print(f"mode={mode} n={n} rcmc compress SQNR {s:.2f} dB")
+    print(f"[measure] rcmc_compress.{mode}.n{n} {s:.3f}")
     assert plan.nonfinite() == 0
     assert s >= RCMC_SQNR_MIN[mode]
 
@@ -378,8 +409,8 @@ def test_rcmc_frame_4096_matches_oracle_metrics(mode):
     Ha = scenes.quantize(oracle.matched_filter(sc.azimuth_replica, 4096), ffmt)
     ref = oracle.rda_rcmc_image(scenes.quantize(sc.echo, fmt), Hr, Ha,
                                 sc.rcmc_shift.astype(np.float32).astype(np.float64))
-    s = metrics.sqnr_db(ref, img, align=True)
-    print(f"mode={mode} RCMC frame SQNR {s:.2f} dB")
+    s = metrics.sqnr_db(ref, img)
+    print(f"[measure] rcmc_frame_sqnr.{mode} {s:.3f}")
     assert np.all(np.isfinite(img))
     assert s >= FRAME_SQNR_MIN[mode]
     for (r0, a0) in sc.targets:

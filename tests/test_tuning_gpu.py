@@ -65,8 +65,8 @@ def test_both_engines_meet_parity():
         plan.set_tuning(engine, 0)
         X = download(plan.forward(upload(x, "fp16")), "fp16")
         s = sqnr_db(oracle.fft(x), X)
-        print(f"engine={engine} SQNR {s:.2f} dB")
-        assert s >= 60.0
+        print(f"[measure] engine{engine}.forward {s:.3f}")
+        assert s >= (62.4 if engine == 0 else 64.5)  # measured 65.4 / 67.5
 
 
 def test_autotune_and_cache(tmp_path, monkeypatch):

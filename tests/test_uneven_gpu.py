@@ -26,13 +26,24 @@ def _oracle_uneven(ub, xq):
     return ref
 
 
-@pytest.mark.parametrize("mode", ["fp16", "fp16_fp32", "fp32"])
+def _scaled_input(ub, mode):
+    """The batch's N(0,1) values, with each inverse transform's input scaled
+    by sqrt(n) (a spectrum whose inverse is O(1)) and everything by 1/8 in
+    the FP8 modes (E4M3 saturates at 448)."""
+    x = ub.x.copy()
+    for i in np.nonzero(ub.inverse)[0]:
+        n = 1 << int(ub.log2n[i])
+        x[ub.offsets[i]:ub.offsets[i] + n] *= np.sqrt(n)
+    return x * (0.125 if mode in ("e4m3", "e5m2") else 1.0)
+
+
+@pytest.mark.parametrize("mode", ["fp16", "fp16_fp32", "fp16_mul_fp32_acc", "fp32", "e4m3", "e5m2"])
 def test_uneven_small_matches_oracle(mode):
     need_gpu()
     announce(f"uneven 300 transforms mode={mode}")
     ub = scenes.uneven_batch(seed=4, count=300)
     fmt = api.storage_format(mode)
-    xq = scenes.quantize(ub.x, fmt)
+    xq = scenes.quantize(_scaled_input(ub, mode), fmt)
     plan = api.UnevenPlan(ub.log2n, ub.inverse, mode, flags=api.FLAG_CHECK_FINITE)
     assert plan.total == xq.size and np.array_equal(plan.offsets, ub.offsets)
     y = download(plan.execute(upload(xq, fmt)), fmt)
@@ -45,7 +56,10 @@ def test_uneven_small_matches_oracle(mode):
                 continue
             sel = np.concatenate([np.arange(ub.offsets[i], ub.offsets[i] + (1 << e)) for i in idx])
             s = sqnr_db(ref[sel], y[sel])
-            assert s >= FWD_SQNR_MIN[mode] - 4.0, (e, inv, s)
+            print(f"[measure] uneven.{mode}.n{1 << e}.{'inv' if inv else 'fwd'} {s:.3f}")
+            # measured minima over the seven sizes: 1.5 dB under the N = 4096
+            # forward bar covers the extra pass at 8192 and 16384
+            assert s >= FWD_SQNR_MIN[mode] - 1.5, (e, inv, s)
 
 
 def test_uneven_full_config_equals_per_size_launches():
@@ -80,7 +94,7 @@ def test_uneven_full_config_equals_per_size_launches():
         n = 1 << int(ub.log2n[i])
         seg = xq[ub.offsets[i]:ub.offsets[i] + n]
         ref = oracle.fft(seg[None], inverse=bool(ub.inverse[i]))[0]
-        assert sqnr_db(ref, yq[ub.offsets[i]:ub.offsets[i] + n]) >= 50.0
+        assert sqnr_db(ref, yq[ub.offsets[i]:ub.offsets[i] + n]) >= 56.0  # 59.8 at worst
 
 
 def test_uneven_empty_and_single():
@@ -90,6 +104,6 @@ def test_uneven_empty_and_single():
     x = scenes.quantize(scenes.gaussian_rows(9, 1, 16384)[0], "fp16")
     p1 = api.UnevenPlan([14], [0], "fp16")
     y = download(p1.execute(upload(x, "fp16")), "fp16")
-    assert sqnr_db(oracle.fft(x[None])[0], y) >= 52.0
+    assert sqnr_db(oracle.fft(x[None])[0], y) >= 56.0
     with pytest.raises(api._lib.BfpError):
         api.UnevenPlan([7], [0], "fp16")
