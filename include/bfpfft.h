@@ -314,6 +314,18 @@ int sar_azimuth_compress(bfp_plan az_plan, const void *rc_t, void *image, const 
 int sar_image_entropy(bfp_plan plan, const void *image, long long count, double *stats,
                       void *stream);
 
+/* sar_image_entropy without a plan and without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid it): the same kernels and the same
+ * fixed-order sums, so the result equals sar_image_entropy's bit for bit.
+ * The per-workgroup partial sums live in a library-owned device array of
+ * 1024 (S, Q) pairs (16 KiB, held on each GPU the library runs on until the
+ * process ends); a launch uses min(ceil(count / 256), 1024) workgroups.
+ * count in [1, 2^40] (else BFP_EINVAL); image: count FP32 pairs; stats:
+ * (device) 3 doubles.  Calls that overlap on one GPU share the array and
+ * race: serialise them (one stream, or events). */
+int sar_image_entropy_noalloc(const void *image, long long count, double *stats, void *stream);
+
 /* The image of sar_azimuth_compress (phase applied before the chain, output
  * FP32 pairs) and its entropy statistics in one pass: each workgroup of the
  * compression reduces |I|^2 and |I|^2 ln |I|^2 of the rows it wrote

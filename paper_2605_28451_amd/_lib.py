@@ -72,6 +72,7 @@ SIGNATURES = {
     "sar_corner_turn": (_I, [_P, _P, _I, _I, _I, _P]),
     "sar_azimuth_compress": (_I, [_P, _P, _P, _P, _P, _I, _I, _U, _P]),
     "sar_image_entropy": (_I, [_P, _P, _LL, _P, _P]),
+    "sar_image_entropy_noalloc": (_I, [_P, _LL, _P, _P]),
     "sar_azimuth_image_entropy": (_I, [_P, _P, _P, _P, _P, _I, _P, _P]),
     "sar_entropy_grad": (_I, [_P, _P, _P, _P, _LL, _P]),
     "sar_azimuth_phase_grad": (_I, [_P, _P, _P, _P, _P, _P, _P, _I, _P]),

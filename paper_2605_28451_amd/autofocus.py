@@ -16,6 +16,19 @@ from ._lib import FLAG_AUTOFOCUS, check
 from .api import FFTPlan, _check_storage, _ptr, _stream
 
 
+def image_entropy_noalloc(img, stats=None, stream=None):
+    """(S, Q, E) of an FP32 image with no plan and no device allocation by the
+    library (its partial sums live in a library-owned device array; calls on
+    one GPU must not overlap).  `stats`: 3 float64 on the device, or None."""
+    count = img.numel() // 2
+    _check_storage(img, "fp32", count, "image")
+    if stats is None:
+        stats = torch.empty(3, dtype=torch.float64, device=img.device)
+    check(_lib.load().sar_image_entropy_noalloc(_ptr(img), count, _ptr(stats), _stream(stream)),
+          "sar_image_entropy_noalloc")
+    return stats
+
+
 class AutofocusPlan(FFTPlan):
     """Azimuth plan (n = pulses, batch = range bins) with the autofocus workspace."""
 

@@ -546,6 +546,15 @@ int sar_image_entropy(bfp_plan plan, const void *image, long long count, double 
   return e == hipSuccess ? BFP_OK : hip_fail(e, "entropy launch");
 }
 
+int sar_image_entropy_noalloc(const void *image, long long count, double *stats, void *stream) {
+  if (count < 1 || count > bfp::kEntropyNoAllocMaxCount)
+    return fail(BFP_EINVAL, "count must lie in [1, 2^40]: the no-allocation entropy reduces at most "
+                            "2^40 values through its fixed 1024-workgroup scratch");
+  if (!image || !stats) return fail(BFP_EINVAL, "NULL pointer");
+  hipError_t e = bfp::launch_entropy_noalloc(image, count, stats, (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "no-allocation entropy launch");
+}
+
 int sar_azimuth_image_entropy(bfp_plan az_plan, const void *rc_t, void *image, const void *h_az,
                               const float *phase, int n_range, double *stats, void *stream) {
   int st = check_rows_plan(az_plan);

@@ -16,6 +16,8 @@
 // and the per-pulse accumulation of Im(G_z conj z).  Each workgroup
 // accumulates its rows in registers and writes one partial row; a second
 // kernel sums the partial rows in a fixed order (deterministic).
+#include <mutex>
+
 #include "fft_engine.hpp"
 #include "internal.hpp"
 
@@ -96,6 +98,45 @@ hipError_t launch_entropy(const void *img, long long count, double *partial, dou
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(entropy_final_kernel, dim3(1), dim3(256), 0, s, partial, (int)blocks, stats);
   return hipGetLastError();
+}
+
+// ------------------------------------------- entropy without allocation ----
+// The plan-free variant of launch_entropy: the per-workgroup (S, Q) partials
+// live in this file-scope device array instead of a plan's workspace.  Each
+// GPU holds its own copy at its own address, found once per device with
+// hipGetSymbolAddress (the array's name in host code is only a stand-in for
+// the symbol, never a device address).  Every launch writes the partials of
+// all the workgroups it uses before the final kernel reads them, so nothing
+// needs clearing; calls that overlap on one GPU share the array and race.
+static __device__ __align__(256) double scratch[2 * kEntropyNoAllocPartials];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t entropy_scratch(void **ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_entropy_noalloc(const void *img, long long count, double *stats, hipStream_t s) {
+  static_assert(ENT_BLOCKS <= kEntropyNoAllocPartials, "the partials must fit the scratch array");
+  void *ptr = nullptr;
+  hipError_t e = entropy_scratch(&ptr);
+  if (e != hipSuccess) return e;
+  return launch_entropy(img, count, static_cast<double *>(ptr), stats, s);
 }
 
 // dE/dI scaled by an upstream factor: G = g (-2/S)(ln|I|^2 - ln S + E) I

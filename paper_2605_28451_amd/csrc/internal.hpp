@@ -112,6 +112,12 @@ struct PhaseGradArgs {
 hipError_t launch_entropy_final(const double *partial, int blocks, double *stats, hipStream_t s);
 hipError_t launch_entropy(const void *img, long long count, double *partial, double *stats,
                           hipStream_t s);
+// launch_entropy with its partials in a file-scope device array (no
+// allocation); kEntropyNoAllocPartials (S, Q) pairs = 16 KiB per device
+constexpr int kEntropyNoAllocPartials = 1024;
+constexpr int kMaxDevices = 64;
+constexpr long long kEntropyNoAllocMaxCount = 1ll << 40;
+hipError_t launch_entropy_noalloc(const void *img, long long count, double *stats, hipStream_t s);
 hipError_t launch_entropy_grad(const void *img, const double *stats, const float *scale, void *grad,
                                long long count, hipStream_t s);
 hipError_t launch_phase_grad(bool fp16_storage, int log2n, const PhaseGradArgs &a, bool fused,
