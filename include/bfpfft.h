@@ -168,7 +168,29 @@ int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *fi
 int fft_plan_set_tuning(bfp_plan p, int engine, int blocks_per_cu);
 int fft_plan_get_tuning(bfp_plan p, int *engine, int *blocks_per_cu);
 
-/* Times every tuning candidate of the plan on the caller's buffers (op: 0
+/* All tuning knobs: engine and blocks_per_cu as above, and rows_per_thread
+ * (1 or 2): with 2, the forward transform, the BFP inverse (with a filter,
+ * its conjugate or none) and the compression (with a filter, its conjugate,
+ * or a phase applied before the chain) transform two rows per thread
+ * together, sharing twiddles and one barrier per LDS exchange; the other
+ * variants, the matrix-core engine and sizes whose two rows would not leave
+ * LDS for two workgroups per CU (FP32 exchanges above 4096 points, FP16
+ * above 8192) ignore it.  Results are the same bits for every setting.
+ * Uneven plans take rows_per_thread = 1.  A new plan has {1, -1, 2} in the
+ * modes with FP32 arithmetic (BFP_FP32, BFP_FP16_STORE_FP32_COMPUTE and the
+ * FP8-storage modes) and {1, -1, 1} in BFP_FP16 and BFP_FP16_MUL_FP32_ACC.
+ * Errors: BFP_EINVAL. */
+typedef struct {
+  int engine;
+  int blocks_per_cu;
+  int rows_per_thread;
+} bfp_tuning;
+int fft_plan_set_tuning_ex(bfp_plan p, const bfp_tuning *t);
+int fft_plan_get_tuning_ex(bfp_plan p, bfp_tuning *t);
+
+/* Times every tuning candidate of the plan (engine x blocks_per_cu x
+ * rows_per_thread for rows plans, blocks_per_cu for uneven plans) on the
+ * caller's buffers (op: 0
  * forward, 1 BFP inverse with `filter` (may be NULL), 2 fused compression
  * with `filter`; ignored for uneven plans), `reps` calls each after two
  * warm-up calls, keeps the fastest in the plan and returns its mean time per

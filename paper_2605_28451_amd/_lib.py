@@ -56,6 +56,8 @@ SIGNATURES = {
     "fft_plan_nonfinite": (_I, [_P, _P, ctypes.POINTER(ctypes.c_ulonglong)]),
     "fft_plan_set_tuning": (_I, [_P, _I, _I]),
     "fft_plan_get_tuning": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "fft_plan_set_tuning_ex": (_I, [_P, _P]),
+    "fft_plan_get_tuning_ex": (_I, [_P, _P]),
     "fft_autotune": (_I, [_P, _I, _P, _P, _P, _I, ctypes.POINTER(ctypes.c_float), _P]),
     "fft_plan_uneven": (_I, [ctypes.POINTER(_P), _I, _P, _P, _I, _U]),
     "fft_uneven_offsets": (_I, [_P, ctypes.POINTER(_LL)]),

@@ -122,6 +122,12 @@ def corner_turn(x, fmt: str, out=None, stream=None):
     return out
 
 
+class Tuning(ctypes.Structure):
+    """bfp_tuning: the knobs of fft_plan_set_tuning_ex."""
+    _fields_ = [("engine", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
+                ("rows_per_thread", ctypes.c_int)]
+
+
 class FFTPlan:
     """Batched length-n transforms in one precision mode (see include/bfpfft.h)."""
 
@@ -253,6 +259,15 @@ class FFTPlan:
         check(_lib.load().fft_plan_get_tuning(self._h, ctypes.byref(e), ctypes.byref(b)),
               "fft_plan_get_tuning")
         return int(e.value), int(b.value)
+
+    def set_tuning_ex(self, engine: int = 1, blocks_per_cu: int = -1, rows_per_thread: int = 1):
+        t = Tuning(int(engine), int(blocks_per_cu), int(rows_per_thread))
+        check(_lib.load().fft_plan_set_tuning_ex(self._h, ctypes.byref(t)), "fft_plan_set_tuning_ex")
+
+    def get_tuning_ex(self):
+        t = Tuning()
+        check(_lib.load().fft_plan_get_tuning_ex(self._h, ctypes.byref(t)), "fft_plan_get_tuning_ex")
+        return int(t.engine), int(t.blocks_per_cu), int(t.rows_per_thread)
 
     def autotune_on(self, op: int, x, out, filt=None, reps: int = 20, stream=None) -> float:
         """Time every tuning candidate on (x, out), keep the fastest; returns ms/call."""

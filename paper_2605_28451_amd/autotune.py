@@ -1,8 +1,8 @@
 """Autotuner driver with a JSON cache.
 
 The timing loop runs in the library (fft_autotune: every candidate of the
-plan's tuning space -- engine and persistent-grid size -- timed with HIP
-events on the caller's buffers); this module keys the winners by device
+plan's tuning space -- engine, persistent-grid size and rows per thread --
+timed with HIP events on the caller's buffers); this module keys the winners by device
 architecture, size, precision, operation and batch bucket and stores them in
 ``$BFP_AUTOTUNE_CACHE`` (default ``~/.cache/bfpfft/autotune.json``), so later
 plans of the same shape start from the tuned configuration.
@@ -50,8 +50,15 @@ def apply_cached(plan, op: str = "forward") -> bool:
     entry = _load().get(_key(plan, op))
     if entry is None:
         return False
-    plan.set_tuning(entry["engine"], entry["blocks_per_cu"])
+    _apply(plan, entry)
     return True
+
+
+def _apply(plan, entry):
+    if hasattr(plan, "set_tuning_ex"):
+        plan.set_tuning_ex(entry["engine"], entry["blocks_per_cu"], entry.get("rows_per_thread", 1))
+    else:
+        plan.set_tuning(entry["engine"], entry["blocks_per_cu"])
 
 
 def tune(plan, op: str, x, out, filt=None, reps: int = 20, force: bool = False) -> dict:
@@ -59,10 +66,13 @@ def tune(plan, op: str, x, out, filt=None, reps: int = 20, force: bool = False) 
     d = _load()
     k = _key(plan, op)
     if not force and k in d:
-        plan.set_tuning(d[k]["engine"], d[k]["blocks_per_cu"])
+        _apply(plan, d[k])
         return d[k]
     ms = plan.autotune_on(OPS.get(op, 0), x, out, filt, reps)
-    e, b = plan.get_tuning()
-    d[k] = {"engine": e, "blocks_per_cu": b, "ms": ms}
+    if hasattr(plan, "get_tuning_ex"):
+        e, b, rr = plan.get_tuning_ex()
+    else:
+        (e, b), rr = plan.get_tuning(), 1
+    d[k] = {"engine": e, "blocks_per_cu": b, "rows_per_thread": rr, "ms": ms}
     _save(d)
     return d[k]

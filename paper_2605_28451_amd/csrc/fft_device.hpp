@@ -25,6 +25,12 @@ struct __attribute__((aligned(8))) c32 {
 };
 
 // ------------------------------------------------------------ FP32 ops ---
+// Contraction is off in these helpers and the complex products use explicit
+// FMAs: with the compiler free to fuse a product into whichever neighbouring
+// add it finds, two kernels doing the same arithmetic on the same data
+// (one row or two rows per thread, a fused or a separate pass) could round
+// differently.  Written out, every kernel gets the same bits.
+#define BFP_NO_CONTRACT _Pragma("clang fp contract(off)")
 __device__ __forceinline__ c32 mk(float x, float y) { return c32{x, y}; }
 __device__ __forceinline__ c32 cadd(c32 a, c32 b) { return c32{a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ c32 csub(c32 a, c32 b) { return c32{a.x - b.x, a.y - b.y}; }
@@ -32,22 +38,39 @@ __device__ __forceinline__ c32 csub(c32 a, c32 b) { return c32{a.x - b.x, a.y - 
 __device__ __forceinline__ c32 csub_i(c32 a, c32 b) { return c32{a.x + b.y, a.y - b.x}; }
 __device__ __forceinline__ c32 cadd_i(c32 a, c32 b) { return c32{a.x - b.y, a.y + b.x}; }
 __device__ __forceinline__ c32 cmul(c32 a, c32 b) {
-  return c32{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+  BFP_NO_CONTRACT
+  return c32{__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x)};
 }
-__device__ __forceinline__ c32 cscale(c32 a, float s) { return c32{a.x * s, a.y * s}; }
+__device__ __forceinline__ c32 cscale(c32 a, float s) {
+  BFP_NO_CONTRACT
+  return c32{a.x * s, a.y * s};
+}
 __device__ __forceinline__ c32 cconj(c32 a) { return c32{a.x, -a.y}; }
 __device__ __forceinline__ c32 mul_mi(c32 a) { return c32{a.y, -a.x}; }   // x (-i)
 __device__ __forceinline__ c32 mul_pi(c32 a) { return c32{-a.y, a.x}; }   // x (+i)
 __device__ __forceinline__ c32 cneg(c32 a) { return c32{-a.x, -a.y}; }
 // x (c + i s) with compile-time constants
 __device__ __forceinline__ c32 cmulk(c32 a, float c, float s) {
-  return c32{a.x * c - a.y * s, a.x * s + a.y * c};
+  BFP_NO_CONTRACT
+  return c32{__builtin_fmaf(a.x, c, -(a.y * s)), __builtin_fmaf(a.x, s, a.y * c)};
 }
 // x k (1 - i), x k (-1 - i), x k (-1 + i), x k (1 + i)
-__device__ __forceinline__ c32 mul_1mi(c32 a, float k) { return c32{(a.x + a.y) * k, (a.y - a.x) * k}; }
-__device__ __forceinline__ c32 mul_m1mi(c32 a, float k) { return c32{(a.y - a.x) * k, -(a.x + a.y) * k}; }
-__device__ __forceinline__ c32 mul_m1pi(c32 a, float k) { return c32{-(a.x + a.y) * k, (a.x - a.y) * k}; }
-__device__ __forceinline__ c32 mul_1pi(c32 a, float k) { return c32{(a.x - a.y) * k, (a.x + a.y) * k}; }
+__device__ __forceinline__ c32 mul_1mi(c32 a, float k) {
+  BFP_NO_CONTRACT
+  return c32{(a.x + a.y) * k, (a.y - a.x) * k};
+}
+__device__ __forceinline__ c32 mul_m1mi(c32 a, float k) {
+  BFP_NO_CONTRACT
+  return c32{(a.y - a.x) * k, -(a.x + a.y) * k};
+}
+__device__ __forceinline__ c32 mul_m1pi(c32 a, float k) {
+  BFP_NO_CONTRACT
+  return c32{-(a.x + a.y) * k, (a.x - a.y) * k};
+}
+__device__ __forceinline__ c32 mul_1pi(c32 a, float k) {
+  BFP_NO_CONTRACT
+  return c32{(a.x - a.y) * k, (a.x + a.y) * k};
+}
 
 // ----------------------------------------------------- packed FP16 ops ---
 __device__ __forceinline__ h2 cadd(h2 a, h2 b) { return a + b; }

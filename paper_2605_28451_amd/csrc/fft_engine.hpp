@@ -341,6 +341,107 @@ struct Engine {
     }
   }
 
+  // ---- several rows per thread ----
+  // RR independent transforms (rows) per thread: every pass reads, twiddles
+  // and butterflies all RR rows before the next exchange, so the rows share
+  // the twiddle registers and one barrier per exchange, and one row's LDS
+  // latency is covered by the other rows' arithmetic.  Row r of a buffer
+  // sits at buf[b] + r LDS_N.  NB = 2: buffers alternate as in pass_db (one
+  // barrier per exchange); NB = 1: one buffer, a barrier before its writes
+  // too.  MID() runs between the twiddle products and the butterflies (the
+  // next pass's twiddle loads, where twiddles come from memory).
+  template <int PASS, bool CJ, int RR, int NB, class Mid>
+  static __device__ __forceinline__ void pass_rr(Comp (&v)[RR][E], Lds *const (&buf)[2], unsigned &x,
+                                                 int t, const Tw (&w)[E], Mid mid) {
+    constexpr int R = G::radix(PASS);
+    constexpr int NS = G::span(PASS);
+    constexpr int B = E / R;
+    constexpr bool LAST = (PASS == G::S::P - 1);
+    if constexpr (PASS > 0) {
+      const Lds *rd = buf[NB == 2 ? ((x - 1) & 1) : 0];
+      typedef Pad<LOG2N, PASS - 1> In;
+      const int tp = In::at(t);
+#pragma unroll
+      for (int q = 0; q < RR; ++q) {
+        Lds raw[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) raw[e] = rd[q * G::LDS_N + lds_slot<In, T>(tp, e)];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          v[q][b] = M::from_lds(raw[b]);
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[q][b + B * r] = M::twiddle(raw[b + B * r], w[b * R + r]);
+        }
+      }
+    }
+    mid();
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        Comp u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[q][b + B * r];
+        dft<R, CJ && LAST && kFoldConj>(u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][b + B * r] = u[r];
+      }
+    }
+    if constexpr (!LAST) {
+      typedef Pad<LOG2N, PASS> Out;
+      static_assert(pad_splits<Out, G::N, R, NS>(), "padded offsets of a butterfly must not straddle a pad");
+      if constexpr (NB == 1) __syncthreads();  // the reads of the previous exchange are done
+      Lds *wr = buf[NB == 2 ? (x & 1) : 0];
+#pragma unroll
+      for (int q = 0; q < RR; ++q) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          const int pbase = stockham_base<Out, R, NS>((unsigned)t + T * b);
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            wr[q * G::LDS_N + pbase + pad_off<Out>(r * NS)] = M::to_lds(v[q][b + B * r]);
+        }
+      }
+      __syncthreads();
+      ++x;
+    }
+  }
+
+  template <bool CJ, int RR>
+  static __device__ __forceinline__ void conj_unfolded_rr(Comp (&v)[RR][E]) {
+    if constexpr (CJ && !kFoldConj) {
+#pragma unroll
+      for (int q = 0; q < RR; ++q)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[q][e] = conj_store(v[q][e]);
+    }
+  }
+
+  // RR rows with register twiddles, two buffers.
+  template <bool CJ, int RR>
+  static __device__ __forceinline__ void run_regs_rr(Comp (&v)[RR][E], Lds *const (&buf)[2], unsigned &x,
+                                                     int t, TwRegs &W) {
+    static_assert(kTwRegs, "register twiddles need packed FP16 data and twiddles and at most 3 passes");
+    auto none = [] {};
+    pass_rr<0, CJ, RR, 2>(v, buf, x, t, W.w[0], none);
+    if constexpr (G::S::P > 1) pass_rr<1, CJ, RR, 2>(v, buf, x, t, W.w[0], none);
+    if constexpr (G::S::P > 2) pass_rr<2, CJ, RR, 2>(v, buf, x, t, W.w[1], none);
+    conj_unfolded_rr<CJ>(v);
+  }
+
+  // RR rows with twiddles loaded from the plan's table one pass ahead.
+  template <bool CJ, int RR, int NB>
+  static __device__ __forceinline__ void run_rr(Comp (&v)[RR][E], Lds *const (&buf)[2], unsigned &x,
+                                                const Tw *__restrict__ tw, int t) {
+    Tw w[E];
+    load_tw<1>(tw, t, w);
+    pass_rr<0, CJ, RR, NB>(v, buf, x, t, w, [] {});
+    if constexpr (G::S::P > 1) pass_rr<1, CJ, RR, NB>(v, buf, x, t, w, [&] { load_tw<2>(tw, t, w); });
+    if constexpr (G::S::P > 2) pass_rr<2, CJ, RR, NB>(v, buf, x, t, w, [&] { load_tw<3>(tw, t, w); });
+    if constexpr (G::S::P > 3) pass_rr<3, CJ, RR, NB>(v, buf, x, t, w, [] {});
+    conj_unfolded_rr<CJ>(v);
+  }
+
   // Forward transform with register twiddles and two LDS buffers (CJ as in
   // run).
   template <bool CJ = false>

@@ -34,6 +34,7 @@ struct RowArgs {
   unsigned long long *nonfinite;  // device counter
   int grid_limit;        // > 0: persistent grid of at most this many workgroups
   int engine;            // 0: matrix cores where available, 1: vector ALU only
+  int rows_per_thread;   // 1, or 2: the multi-row kernel where it covers the variant
   double *ent_partial;   // compression to FP32 with phasor: per-workgroup (S, Q) of the
                          // output's entropy sums (see rows_grid), or NULL
   int *row_exp;          // KF_ADAPT: per-row block exponent of the output, or NULL

@@ -28,6 +28,7 @@ struct bfp_plan_s {
   // tuning knobs (fft_plan_set_tuning / fft_autotune)
   int tune_engine = 1;     // 0: matrix cores where available, 1: vector ALU (default)
   int tune_bpc = 0;        // workgroups per CU of a persistent grid, 0 = default
+  int tune_rr = 1;         // rows per thread (1, or 2: the multi-row kernel)
   int cu_count = 0;
   int uneven_max_bpc = 1;
   // autofocus workspace

@@ -415,6 +415,174 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
   }
 }
 
+// Several rows per thread: the plain forward transform, the BFP inverse
+// (with or without a filter, or its conjugate) and the compression (plain,
+// conjugated filter, phasor before the chain) with RR rows of a group
+// transformed together (Engine::pass_rr: shared twiddles, one barrier per
+// exchange for all RR rows, one row's LDS latency covered by the others'
+// arithmetic).  The arithmetic of each row is that of row_kernel, so the
+// results are the same bits.  PIPE (register twiddles, persistent grids):
+// the next group's rows are loaded while the current group is transformed.
+// Otherwise the twiddles come from the table one pass ahead and a group's
+// rows are loaded at its start.  NB LDS buffers per row (2: one barrier per
+// exchange).  Group g holds rows g TPW RR + q TPW + local, q < RR.
+template <class M, int LOG2N, int OP, int V, bool OUT32, int RR, int NB, bool PIPE>
+__global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel_rr(RowArgs a) {
+  typedef Geometry<LOG2N> G;
+  typedef Engine<M, LOG2N> EN;
+  typedef typename M::Comp Comp;
+  typedef typename M::Store Store;
+  typedef typename M::Filt Filt;
+  typedef typename M::Tw Tw;
+  constexpr int E = G::E, T = G::T, N = G::N;
+  constexpr bool conj_f = (V & V_CONJ) != 0;
+  constexpr bool phasor = (V & V_PHASOR) != 0;
+  static_assert((V & ~(V_CONJ | V_PHASOR)) == 0, "plain, conjugated-filter and phasor variants only");
+  static_assert(!phasor || OP == OP_COMPRESS, "the phasor belongs to the compression");
+  static_assert(!PIPE || (EN::kTwRegs && NB == 2), "the pipelined form keeps its twiddles in registers");
+  __shared__ typename M::Lds lds_all[NB * G::TPW * RR * G::LDS_N];
+  const int local = G::TPW == 1 ? 0 : (int)(threadIdx.x / T);
+  const unsigned t = threadIdx.x & (T - 1);
+  typename M::Lds *lds = lds_all + local * RR * G::LDS_N;
+  typename M::Lds *const buf[2] = {lds, lds + (NB == 2 ? G::TPW * RR * G::LDS_N : 0)};
+  unsigned xch = 0;
+  const Tw *tw = static_cast<const Tw *>(a.tw);
+  const Filt *f = static_cast<const Filt *>(a.filter);
+  constexpr bool kHoist = sizeof(Filt) == 4 && OP != OP_FWD;
+  Filt hf[kHoist ? E : 1];
+  if constexpr (kHoist) {
+    if (f) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) hf[e] = f[t + T * e];
+    }
+  }
+  constexpr int ROWS = G::TPW * RR;
+  const int groups = (a.rows + ROWS - 1) / ROWS;
+  auto row_of = [&](int g, int q) { return (long long)g * ROWS + q * G::TPW + local; };
+  typename EN::TwRegs W;
+  Store nx[PIPE ? RR : 1][E];
+  if constexpr (PIPE) {
+    EN::load_tw_regs(tw, t, W);
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+      const long long r0 = row_of(blockIdx.x, q);
+      if ((int)blockIdx.x < groups && r0 < a.rows) {
+        const Store *src = static_cast<const Store *>(a.in) + r0 * N + t;
+#pragma unroll
+        for (int e = 0; e < E; ++e) nx[q][e] = ld_stream(src + (unsigned)(T * e));
+      }
+    }
+  }
+  for (int it = blockIdx.x; it < groups; it += gridDim.x) {
+    // opaque per group: the thread index (else every pass's LDS addresses are
+    // hoisted into registers), the register twiddles and the hoisted filter
+    // (else each FP16 pair is kept twice, pre-broadcast)
+    unsigned tt = t;
+    asm volatile("" : "+v"(tt));
+    if constexpr (PIPE) {
+#pragma unroll
+      for (int p = 0; p < (int)(sizeof(W.w) / sizeof(W.w[0])); ++p)
+#pragma unroll
+        for (int e = 0; e < E; ++e) asm volatile("" : "+v"(W.w[p][e]));
+    }
+    if constexpr (kHoist) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) asm volatile("" : "+v"(hf[e]));
+    }
+    Comp v[RR][E];
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+      const long long row = row_of(it, q);
+      if (row < a.rows) {
+        if constexpr (PIPE) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[q][e] = M::decode(nx[q][e]);
+        } else {
+          const Store *src = static_cast<const Store *>(a.in) + row * N + tt;
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[q][e] = M::load(src, (unsigned)(T * e));
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[q][e] = Comp{};
+      }
+    }
+    if constexpr (phasor) {
+      const c32 *ph = static_cast<const c32 *>(a.phasor) + tt;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const c32 p = ph[T * e];
+#pragma unroll
+        for (int q = 0; q < RR; ++q) v[q][e] = mul_c32(v[q][e], p);
+      }
+    }
+    if constexpr (PIPE) {
+      const int nit = it + (int)gridDim.x;
+#pragma unroll
+      for (int q = 0; q < RR; ++q) {
+        const long long nrow = nit < groups ? row_of(nit, q) : a.rows;
+        if (nrow < a.rows) {
+          const Store *src = static_cast<const Store *>(a.in) + nrow * N + tt;
+#pragma unroll
+          for (int e = 0; e < E; ++e) nx[q][e] = ld_stream(src + (unsigned)(T * e));
+        }
+      }
+    }
+    auto run = [&](auto cj) {
+      if constexpr (PIPE) EN::template run_regs_rr<decltype(cj)::value, RR>(v, buf, xch, tt, W);
+      else EN::template run_rr<decltype(cj)::value, RR, NB>(v, buf, xch, tw, tt);
+    };
+    if constexpr (OP == OP_FWD) {
+      run(std::false_type{});
+    } else {
+      if constexpr (OP == OP_COMPRESS) run(std::false_type{});
+      // BFP fold at the inverse's load: conj(z . H) . 2^-log2N, or with the
+      // conjugated filter conj(z . conj H) = conj(z) . H
+      if (OP == OP_COMPRESS || f) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          Filt h;
+          if constexpr (kHoist) h = hf[e];
+          else h = f[tt + T * e];
+#pragma unroll
+          for (int q = 0; q < RR; ++q)
+            v[q][e] = conj_f ? pow2<LOG2N>(M::fmul(cconj(v[q][e]), h)) : conj_pow2<LOG2N>(M::fmul(v[q][e], h));
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < RR; ++q)
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[q][e] = conj_pow2<LOG2N>(v[q][e]);
+      }
+      run(std::true_type{});
+    }
+    unsigned bad = 0;
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+      const long long row = row_of(it, q);
+      if (row < a.rows) {
+        if constexpr (OUT32) {
+          c32 *dst = static_cast<c32 *>(a.out) + row * N + tt;
+#pragma unroll
+          for (int e = 0; e < E; ++e) st_stream(dst + (unsigned)(T * e), to_c32(v[q][e]));
+        } else {
+          Store *dst = static_cast<Store *>(a.out) + row * N + tt;
+#pragma unroll
+          for (int e = 0; e < E; ++e) M::store(dst, (unsigned)(T * e), v[q][e]);
+        }
+        if (a.flags & KF_CHECK_FINITE) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            c32 z = OUT32 ? to_c32(v[q][e]) : to_c32(M::round_store(v[q][e]));
+            bad += finite_c(z) ? 0u : 1u;
+          }
+        }
+      }
+    }
+    if (bad) atomicAdd(a.nonfinite, (unsigned long long)bad);
+  }
+}
+
 #if BFP_MODE_ID == 3
 // FP16 multiply / FP32 accumulate at N = 4096 on the matrix cores: the same
 // operations as row_kernel (forward, BFP inverse, fused compression), every
@@ -546,6 +714,36 @@ static hipError_t launch_vector(const RowArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The multi-row kernel for RR = a.rows_per_thread > 1, where it covers the
+// variant (returns false otherwise).
+template <int LOG2N, int OP, int V, bool OUT32>
+static bool launch_rr(const RowArgs &a, hipStream_t s, hipError_t &err) {
+  typedef Geometry<LOG2N> G;
+  if constexpr ((V & ~(V_CONJ | V_PHASOR)) != 0 || ((V & V_PHASOR) && OP != OP_COMPRESS)) {
+    return false;
+  } else {
+    constexpr int RR = 2;
+    // LDS per buffer set; two workgroups must fit a CU (160 KiB): two
+    // buffers per row where they do, else one, else no multi-row kernel
+    constexpr long kSet = (long)G::TPW * RR * G::LDS_N * sizeof(typename MODE::Lds);
+    constexpr int NB = 2 * kSet <= 80 * 1024 ? 2 : 1;
+    if constexpr (kSet > 80 * 1024) {
+      return false;
+    } else {
+      if (a.rows_per_thread != 2) return false;
+      unsigned grid = (unsigned)((a.rows + G::TPW * RR - 1) / (G::TPW * RR));
+      if (a.grid_limit > 0 && grid > (unsigned)a.grid_limit) grid = (unsigned)a.grid_limit;
+      constexpr bool kPipe = Engine<MODE, LOG2N>::kTwRegs && NB == 2;
+      if (kPipe && a.grid_limit > 0)
+        hipLaunchKernelGGL((row_kernel_rr<MODE, LOG2N, OP, V, OUT32, RR, 2, kPipe>), dim3(grid), dim3(G::WG), 0, s, a);
+      else
+        hipLaunchKernelGGL((row_kernel_rr<MODE, LOG2N, OP, V, OUT32, RR, NB, false>), dim3(grid), dim3(G::WG), 0, s, a);
+      err = hipGetLastError();
+      return true;
+    }
+  }
+}
+
 // a.tw is the plan's table.  Where a matrix-core engine exists, that table
 // starts with the matrix-core operands and the vector engine's twiddles
 // follow at kMfmaTableBytes: variants without a matrix-core kernel run on
@@ -560,9 +758,13 @@ static hipError_t launch_one(const RowArgs &a, hipStream_t s) {
     }
     RowArgs b = a;
     b.tw = static_cast<const unsigned char *>(a.tw) + kMfmaTableBytes;
+    hipError_t err = hipSuccess;
+    if (launch_rr<LOG2N, OP, V, OUT32>(b, s, err)) return err;
     return launch_vector<LOG2N, OP, V, OUT32>(b, s);
   }
 #endif
+  hipError_t err = hipSuccess;
+  if (launch_rr<LOG2N, OP, V, OUT32>(a, s, err)) return err;
   return launch_vector<LOG2N, OP, V, OUT32>(a, s);
 }
 

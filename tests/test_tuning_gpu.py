@@ -57,6 +57,50 @@ def test_pipelined_kernel_bitwise_equal(n, rows):
             assert torch.equal(a, b), f"{name} blocks_per_cu={bpc}"
 
 
+@pytest.mark.parametrize("mode", ["fp32", "fp16", "fp16_fp32", "fp16_mul_fp32_acc", "e4m3", "e5m2"])
+@pytest.mark.parametrize("n,rows", [(64, 301), (512, 33), (2048, 9), (4096, 7), (8192, 5), (16384, 3)])
+def test_rows_per_thread_bitwise_equal(mode, n, rows):
+    # two rows per thread (shared twiddles and barriers) must give the bits
+    # of one row per thread, for odd batches (a group's second row absent),
+    # several transforms per workgroup, and persistent grids
+    need_gpu()
+    announce(f"rows per thread mode={mode} n={n} rows={rows}")
+    fmt = api.storage_format(mode)
+    sc = 0.125 if mode in ("e4m3", "e5m2") else 1.0
+    x = upload(scenes.quantize(sc * scenes.gaussian_rows(80 + n, rows, n), fmt), fmt)
+    z = upload(scenes.quantize(sc * np.sqrt(n) * scenes.gaussian_rows(81 + n, rows, n), fmt), fmt)
+    H = api.filter_tensor(scenes.range_replica_padded(n, max(n // 4, 1)), n, mode)
+    ph = torch.tensor(np.random.default_rng(n).uniform(-3, 3, n).astype(np.float32), device="cuda")
+    plan = api.FFTPlan(n, rows, mode)
+    ops = {
+        "forward": lambda: plan.forward(x),
+        "inverse": lambda: plan.inverse_bfp(z),
+        "inverse_filter": lambda: plan.inverse_bfp(z, H),
+        "inverse_conj": lambda: plan.inverse_bfp(z, H, conj_filter=True),
+        "compress": lambda: plan.range_compress(x, H),
+        "compress_fp32": lambda: plan.range_compress(x, H, out_fp32=True),
+        "compress_adjoint": lambda: plan.azimuth_compress(x, H, adjoint=True),
+        "compress_phase": lambda: plan.azimuth_compress(x, H, phase=ph),
+    }
+    plan.set_tuning_ex(1, 0, 1)
+    ref = {k: f().clone() for k, f in ops.items()}
+    for bpc in (0, 1, 3):
+        plan.set_tuning_ex(1, bpc, 2)
+        assert plan.get_tuning_ex() == (1, bpc, 2)
+        for k, f in ops.items():
+            same = torch.equal(f(), ref[k])
+            assert same, f"{k} blocks_per_cu={bpc}: two rows per thread differ from one"
+
+
+def test_default_rows_per_thread():
+    need_gpu()
+    for mode, rr in (("fp32", 2), ("fp16", 1), ("fp16_fp32", 2), ("fp16_mul_fp32_acc", 1),
+                     ("e4m3", 2), ("e5m2", 2)):
+        assert api.FFTPlan(1024, 4, mode).get_tuning_ex() == (1, -1, rr)
+    with pytest.raises(api._lib.BfpError):
+        api.FFTPlan(1024, 4, "fp16").set_tuning_ex(1, 0, 3)
+
+
 def test_both_engines_meet_parity():
     need_gpu()
     x = scenes.quantize(scenes.gaussian_rows(1, 64, 4096), "fp16")
@@ -77,9 +121,10 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     plan = api.FFTPlan(4096, 512, "fp16_mul_fp32_acc")
     e = autotune.tune(plan, "forward", x, out, reps=5)
     assert e["ms"] > 0 and e["engine"] in (0, 1) and e["blocks_per_cu"] in (-1, 0, 1, 2, 3, 4, 5, 6, 8)
+    assert e["rows_per_thread"] in (1, 2)
     plan2 = api.FFTPlan(4096, 512, "fp16_mul_fp32_acc")
     assert autotune.apply_cached(plan2, "forward")
-    assert plan2.get_tuning() == (e["engine"], e["blocks_per_cu"])
+    assert plan2.get_tuning_ex() == (e["engine"], e["blocks_per_cu"], e["rows_per_thread"])
     # tuned plan still correct
     X = download(plan2.forward(x), "fp16")
     xq = scenes.decode(x.cpu().numpy(), "fp16")
