@@ -246,6 +246,35 @@ def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30, inverse=False):
     return res
 
 
+_ORACLE_FRAMES = {}
+
+
+def frame_vs_oracle(sc, mode, img, pts):
+    """The GPU frame against the FP64 oracle's frame of the same storage-
+    rounded echo and filters: unaligned SQNR and the largest per-target
+    differences of PSLR, ISLR, SNR (dB) and IRW (samples)."""
+    import numpy as np
+    import oracle
+    from paper_2605_28451_amd import api, metrics, scenes
+    n = img.shape[0]
+    fmt, ffmt = api.storage_format(mode), api.filter_format(mode)
+    if (fmt, ffmt) not in _ORACLE_FRAMES:
+        Hr = scenes.quantize(oracle.matched_filter(sc.range_replica, n), ffmt)
+        Ha = scenes.quantize(oracle.matched_filter(sc.azimuth_replica, n), ffmt)
+        ref = oracle.sar_image(scenes.quantize(sc.echo, fmt), Hr, Ha)
+        _ORACLE_FRAMES[(fmt, ffmt)] = (ref, [metrics.point_target(ref, r0, a0, noise_patch=(r0 + 300, a0 + 300))
+                                             for (r0, a0) in sc.targets])
+    ref, ref_pts = _ORACLE_FRAMES[(fmt, ffmt)]
+    d = {k: max(abs(p[k] - q[k]) for p, q in zip(pts, ref_pts))
+         for k in ("pslr_range", "pslr_azimuth", "islr_range", "islr_azimuth", "snr", "irw_range",
+                   "irw_azimuth")}
+    return {"sqnr_db": _finite_or_none(metrics.sqnr_db(ref, img), 2),
+            "max_abs_delta_pslr_db": _finite_or_none(max(d["pslr_range"], d["pslr_azimuth"]), 3),
+            "max_abs_delta_islr_db": _finite_or_none(max(d["islr_range"], d["islr_azimuth"]), 3),
+            "max_abs_delta_snr_db": _finite_or_none(d["snr"], 3),
+            "max_abs_delta_irw_samples": _finite_or_none(max(d["irw_range"], d["irw_azimuth"]), 4)}
+
+
 def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False, streams=1):
     """Full 4096x4096 range-Doppler frame: fused range compression, LDS-tiled
     corner turn, fused azimuth compression (fused_ct: the corner turn folded
@@ -329,7 +358,13 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
     return res
 
 
-def bench_uneven(mode, steps, warmup):
+def bench_uneven(mode, steps, warmup, with_sqnr=True):
+    """The 20,000-transform uneven batch (N log-uniform in 256..16384,
+    random directions) in one persistent launch: the plan's grid autotuned
+    on the batch, the launch (queue reset + persistent kernel) captured in a
+    HIP graph and replayed over two rotating buffer sets; eager launches
+    timed beside it; SQNR per size and direction against the FP64 oracle."""
+    import numpy as np
     import torch
     from paper_2605_28451_amd import api, scenes
     ub = scenes.uneven_batch(seed=4, count=20000)
@@ -339,26 +374,71 @@ def bench_uneven(mode, steps, warmup):
     ins = [x0, x0.clone()]
     outs = [torch.empty_like(x0) for _ in range(sets)]
     plan = api.UnevenPlan(ub.log2n, ub.inverse, mode)
-    ms, total = time_launches(lambda i: plan.execute(ins[i], out=outs[i]), sets, steps, warmup)
+    tuned_ms = plan.autotune_on(0, ins[0], outs[0], reps=10)
+    tuning = plan.get_tuning()
+    ms_eager, _ = time_launches(lambda i: plan.execute(ins[i], out=outs[i]), sets, steps, warmup)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for i in range(sets):
+                plan.execute(ins[i], out=outs[i])
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    reps = max(1, steps // sets)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (reps * sets)
     sizes = (1 << ub.log2n.astype("int64"))
-    import numpy as np
     flops = float(np.sum(5.0 * sizes * ub.log2n))
     bytes_ = 2 * x0.numel() * x0.element_size()
-    res = {"mode": mode, "transforms": 20000, "ms_per_launch": ms,
+    res = {"mode": mode, "transforms": 20000, "ms_per_launch": ms, "ms_per_launch_eager": ms_eager,
+           "graph": "queue reset + persistent kernel captured, 2 rotating buffer sets per replay",
+           "autotuned_workgroups_per_cu": tuning[1], "autotune_ms": tuned_ms,
            "gflops": flops / (ms * 1e-3) / 1e9, "hbm_gbs": bytes_ / (ms * 1e-3) / 1e9,
            "bytes_per_launch": bytes_}
+    if with_sqnr:
+        import oracle
+        from paper_2605_28451_amd.metrics import sqnr_db
+        xq = api.to_host(ins[0], fmt)
+        y = api.to_host(outs[0], fmt)
+        per = {}
+        for e in range(8, 15):
+            for inv in (0, 1):
+                idx = np.nonzero((ub.log2n == e) & (ub.inverse == inv))[0]
+                if idx.size == 0:
+                    continue
+                nn = 1 << e
+                sel = (ub.offsets[idx][:, None] + np.arange(nn)[None]).ravel()
+                ref = oracle.fft(xq[sel].reshape(idx.size, nn), inverse=bool(inv))
+                per[f"{nn}_{'inverse_bfp' if inv else 'forward'}"] = {
+                    "transforms": int(idx.size),
+                    "sqnr_db_vs_fp64_oracle": round(sqnr_db(ref, y[sel].reshape(idx.size, nn)), 2)}
+        res["sqnr_by_size"] = per
     del ins, outs, x0
     torch.cuda.empty_cache()
     return res
 
 
-def bench_autofocus(steps, lr=0.3):
-    """50 Adam steps of entropy autofocus on a 4096x4096 frame with the
-    injected per-pulse phase error; returns ms/step and PSLR before/after."""
+def bench_autofocus(steps, lr_max=2.5, lr_min=0.02, with_oracle=True):
+    """`steps` Adam steps (cosine learning-rate schedule from lr_max to
+    lr_min, read on the device) of entropy autofocus on the 4096x4096 frame
+    with the injected per-pulse phase error: ms per step (graph replay and
+    eager), entropy and azimuth PSLR/ISLR before and after, beside the image
+    the FP64 oracle forms with the true correction, and the GPU gradient at
+    phase 0 against FP64 central differences of the oracle's entropy."""
     import numpy as np
     import torch
-    from paper_2605_28451_amd import api, scenes
-    from paper_2605_28451_amd.autofocus import AutofocusLoop, AutofocusPlan, entropy_and_grad
+    from paper_2605_28451_amd import api, metrics, scenes
+    from paper_2605_28451_amd.autofocus import (AutofocusLoop, AutofocusPlan, cosine_schedule,
+                                                entropy_and_grad)
     n = 4096
     perr = scenes.autofocus_phase_error(seed=5, n_pulse=n)
     sc = scenes.sar_scene(seed=3, phase_error=perr)
@@ -369,13 +449,14 @@ def bench_autofocus(steps, lr=0.3):
     rct = api.corner_turn(rc, "fp16")
     plan = AutofocusPlan(n, n, mode)
     Ha = api.filter_tensor(sc.azimuth_replica, n, mode)
+    sched = cosine_schedule(steps, lr_max, lr_min)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def run(graph):
-        """`steps` Adam iterations from phase 0 (library kernels only; one
-        captured iteration replayed per step when graph)."""
+        """`steps` iterations from phase 0 (library kernels only; one captured
+        iteration replayed per step when graph)."""
         phi = torch.zeros(n, dtype=torch.float32, device="cuda")
-        loop = AutofocusLoop(plan, rct, Ha, phi, lr=lr, graph=graph)
+        loop = AutofocusLoop(plan, rct, Ha, phi, graph=graph, lr_schedule=sched)
         E0 = float(loop.entropy())
         img0 = api.to_host(loop.img, "fp32")
         torch.cuda.synchronize()
@@ -400,10 +481,40 @@ def bench_autofocus(steps, lr=0.3):
     e1.record()
     torch.cuda.synchronize()
     ms_grad = e0.elapsed_time(e1) / steps
-    return {"ms_per_step": ms, "ms_per_step_eager": ms_eager, "ms_per_gradient": ms_grad,
-            "graph_equals_eager": bool(torch.equal(phi_g, phi_e)), "steps": steps, "lr": lr,
-            "entropy_before": E0,
-            "entropy_after": float(E), "_img0": img0, "_img1": img1, "_scene": sc}
+
+    def az(im):
+        pts = [metrics.point_target(im, r0, a0, search=64) for (r0, a0) in sc.targets]
+        return (float(np.mean([p["pslr_azimuth"] for p in pts])),
+                float(np.mean([p["islr_azimuth"] for p in pts])))
+
+    out = {"ms_per_step": ms, "ms_per_step_eager": ms_eager, "ms_per_gradient": ms_grad,
+           "graph_equals_eager": bool(torch.equal(phi_g, phi_e)), "steps": steps,
+           "lr_schedule": f"cosine {lr_max} -> {lr_min} over {steps} steps (device-side)",
+           "entropy_before": E0, "entropy_after": float(E)}
+    out["pslr_azimuth_db_before"], out["islr_azimuth_db_before"] = az(img0)
+    out["pslr_azimuth_db_after"], out["islr_azimuth_db_after"] = az(img1)
+    if with_oracle:
+        import oracle
+        rct_h = api.to_host(rct, "fp16")
+        Haq = scenes.quantize(oracle.matched_filter(sc.azimuth_replica, n), "fp16")
+        E_true, _, img_true = oracle.autofocus(rct_h, Haq, -perr, want_image=True)
+        out["entropy_focused_oracle"] = float(E_true)
+        out["pslr_azimuth_db_focused_oracle"], out["islr_azimuth_db_focused_oracle"] = az(img_true)
+        # the GPU gradient at phase 0 against the FP64 analytic gradient and
+        # FP64 central differences of the oracle's entropy (3 largest pulses)
+        z = torch.zeros(n, dtype=torch.float32, device="cuda")
+        _, g_gpu, _ = entropy_and_grad(plan, rct, Ha, z)
+        g_gpu = g_gpu.cpu().numpy().astype(np.float64)
+        _, g_ref = oracle.autofocus(rct_h, Haq, np.zeros(n))
+        fd_err, h = 0.0, 1e-4
+        for m in np.argsort(-np.abs(g_ref))[:3]:
+            pp = np.zeros(n); pp[m] = h
+            fd = (oracle.autofocus(rct_h, Haq, pp)[0] - oracle.autofocus(rct_h, Haq, -pp)[0]) / (2 * h)
+            fd_err = max(fd_err, abs(g_gpu[m] - fd) / abs(fd))
+        out["gradient_rel_err_vs_fp64_analytic"] = float(np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref))
+        out["gradient_max_rel_err_vs_fp64_central_differences"] = float(fd_err)
+    out["_img0"], out["_img1"], out["_scene"] = img0, img1, sc
+    return out
 
 
 def cpu_baseline(sample_in, replica, n, sample_out):
@@ -697,9 +808,9 @@ def main():
         if args.section == "sar_frame":
             r = bench_sar_frame("fp16", args.steps, args.warmup)
         elif args.section == "uneven":
-            r = bench_uneven("fp16", args.steps, args.warmup)
+            r = bench_uneven("fp16", args.steps, args.warmup, with_sqnr=False)
         else:
-            r = bench_autofocus(args.steps)
+            r = bench_autofocus(args.steps, with_oracle=False)
         print(f"[section] {args.section}: " + json.dumps(
             {k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()
              if not k.startswith("_")}), file=sys.stderr, flush=True)
@@ -789,6 +900,8 @@ def main():
         r = bench_fft("fp16", 64, n, args.steps, args.warmup, min_bytes=0)
         fft["fp16_batch64"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}
         out["fft_n4096"] = fft
+        # the same ratio on the plain forward FFT (1 GiB each way, both modes)
+        out["fp16_over_fp32_plain_fft"] = round(fft["fp16"]["gflops"] / fft["fp32"]["gflops"], 3)
         from paper_2605_28451_amd import metrics as _m  # noqa: F401  (metrics of the GPU image only)
         sar = {}
         imgs = {}
@@ -806,6 +919,8 @@ def main():
                 for k, key, nd in (("pslr_range_db_mean", "pslr_range", 3),
                                    ("pslr_azimuth_db_mean", "pslr_azimuth", 3),
                                    ("snr_db_mean", "snr", 2))}
+            if not args.no_cpu:
+                sar[mode]["image"]["vs_fp64_oracle"] = frame_vs_oracle(sc, mode, r["_img"], pts)
         sar_fp16_img = imgs["fp16"]
         sar["fp16_metrics"] = sar["fp16"]["image"]
         # image SQNR of every mode against the FP32 path's image (real scale aligned)
@@ -857,22 +972,11 @@ def main():
         ub = bench_uneven("fp16", args.steps, args.warmup)
         out["uneven_20000"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in ub.items()}
         log("autofocus 50 Adam steps 4096x4096")
-        af = bench_autofocus(50)
-        sc = af["_scene"]
-        before = [_m.point_target(af["_img0"], r0, a0, search=64) for (r0, a0) in sc.targets]
-        after = [_m.point_target(af["_img1"], r0, a0, search=64) for (r0, a0) in sc.targets]
+        af = bench_autofocus(50, with_oracle=not args.no_cpu)
         out["autofocus_4096"] = {
-            "ms_per_step": round(af["ms_per_step"], 4), "ms_per_step_eager": round(af["ms_per_step_eager"], 4),
-            "ms_per_gradient": round(af["ms_per_gradient"], 4),
-            "step": "image + entropy, fused phase gradient, Adam (library kernels), one HIP graph replay per step",
-            "graph_equals_eager": af["graph_equals_eager"],
-            "steps": af["steps"], "lr": af["lr"],
-            "entropy_before": round(af["entropy_before"], 5), "entropy_after": round(af["entropy_after"], 5),
-            "pslr_azimuth_db_before": round(float(np.mean([p["pslr_azimuth"] for p in before])), 2),
-            "pslr_azimuth_db_after": round(float(np.mean([p["pslr_azimuth"] for p in after])), 2),
-            "peak_power_gain_db": round(float(10 * np.log10(np.mean([p["peak_power"] for p in after]) /
-                                                          np.mean([p["peak_power"] for p in before]))), 2),
-        }
+            k: (round(v, 4) if isinstance(v, float) else v) for k, v in af.items() if not k.startswith("_")}
+        out["autofocus_4096"]["step"] = ("image + entropy, fused phase gradient, Adam (library kernels), "
+                                         "one HIP graph replay per step")
         if not args.no_cpu:
             log("cpu oracle on the other workloads (context)")
             out["cpu_baseline"]["other_workloads"] = cpu_oracle_workloads()

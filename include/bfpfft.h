@@ -391,6 +391,16 @@ int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, co
 int sar_autofocus_adam(float *phase, const float *grad, float *m, float *v, unsigned *step, int n,
                        float lr, float beta1, float beta2, float eps, void *stream);
 
+/* sar_autofocus_adam with a learning-rate schedule read on the device, so a
+ * graph-captured iteration follows it on every replay: step k (the updated
+ * *step) uses lr_schedule[min(k, schedule_len) - 1]; (device) lr_schedule
+ * holds schedule_len floats, each finite and >= 0 (any other entry gives a
+ * zero step).  schedule_len in [1, 2^20]; the other arguments as for
+ * sar_autofocus_adam.  Errors: BFP_EINVAL before any launch. */
+int sar_autofocus_adam_schedule(float *phase, const float *grad, float *m, float *v, unsigned *step,
+                                int n, const float *lr_schedule, int schedule_len, float beta1,
+                                float beta2, float eps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

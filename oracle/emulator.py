@@ -11,7 +11,13 @@ Two harnesses, both written from the text of the paper:
   fused-multiply-add FFT formulation of Linzer & Feig (1993).
 * ``storage_fft`` -- Sec. VII / Table V: FP64 arithmetic and twiddles, with
   the data rounded to a storage format (FP16, OCP FP8 E4M3 or E5M2,
-  saturating) after the input and after every radix-2 stage.
+  saturating) after the input and after every radix-2 stage.  Two of the
+  precision-recovery ideas the paper names as future work (Sec. VII,
+  Sec. VIII) are options of the same harness: stochastic rounding (round up
+  with probability equal to the distance to the lower neighbour, in units of
+  the spacing), and error feedback, in which each stored value keeps its
+  rounding residual, itself stored in the same format, and the next stage
+  reads the sum of the two (twice the bytes).
 
 Rounding: FP16 sums and products are formed in FP32 and rounded to FP16.
 FP32 carries 24 >= 2*11+2 significand bits, so this double rounding equals a
@@ -54,6 +60,24 @@ def round_to_format(x, fmt: str):
 
 def round_complex(z, fmt: str):
     return round_to_format(z.real, fmt) + 1j * round_to_format(z.imag, fmt)
+
+
+def round_to_format_stochastic(x, fmt: str, u):
+    """Stochastic rounding to ``fmt``: with lo <= x < hi the neighbouring
+    values of the format, x rounds to hi when u < (x - lo) / (hi - lo), else
+    to lo; u are uniform [0, 1) draws of x's shape.  Exact values stay."""
+    mant, emin, vmax, sat = FORMATS[fmt]
+    x = np.asarray(x, dtype=np.float64)
+    ax = np.abs(x)
+    with np.errstate(divide="ignore"):
+        e = np.floor(np.log2(np.where(ax > 0, ax, 1.0)))
+    e = np.maximum(e, emin)
+    q = np.ldexp(1.0, (e - mant).astype(np.int64))
+    lo = np.floor(x / q) * q
+    r = np.where(u < (x - lo) / q, lo + q, lo)
+    if sat:
+        r = np.clip(r, -vmax, vmax)
+    return r
 
 
 def _f16(a):
@@ -138,21 +162,40 @@ def fp16_radix2_fft(x, butterfly: str = "standard"):
     return ar.astype(np.float64) + 1j * ai.astype(np.float64)
 
 
-def storage_fft(x, fmt: str):
+def storage_fft(x, fmt: str, rounding: str = "rne", feedback: bool = False, seed: int = 0):
     """Radix-2 Stockham FFT in FP64 arithmetic with FP64 twiddles, rounding the
-    data to ``fmt`` after the input and after each of the log2(N) stages."""
+    data to ``fmt`` after the input and after each of the log2(N) stages.
+
+    rounding="stochastic": each rounding is stochastic (uniform draws from
+    numpy's generator seeded with ``seed``).  feedback=True: each stored
+    value is the pair (r, round(x - r)) with r = round(x), both in ``fmt``,
+    and every stage reads their sum."""
     x = np.atleast_2d(np.asarray(x, dtype=np.complex128))
     rows, n = x.shape
     stages = int(np.log2(n))
     w = _twiddles(n)
-    a = round_complex(x, fmt)
+    rng = np.random.default_rng(seed)
+
+    def rnd(v):
+        if rounding == "rne":
+            return round_complex(v, fmt)
+        if rounding == "stochastic":
+            return (round_to_format_stochastic(v.real, fmt, rng.random(v.shape)) +
+                    1j * round_to_format_stochastic(v.imag, fmt, rng.random(v.shape)))
+        raise ValueError(rounding)
+
+    def store(v):
+        r = rnd(v)
+        return r + rnd(v - r) if feedback else r
+
+    a = store(x)
     l, m = 1, n // 2
     for _ in range(stages):
         v = a.reshape(rows, 2, m, l)
         c0, c1 = v[:, 0], v[:, 1]
         t = c1 * w[(np.arange(l) * m)][None, None, :]
         out = np.stack([c0 + t, c0 - t], axis=2)
-        a = round_complex(out.reshape(rows, n), fmt)
+        a = store(out.reshape(rows, n))
         l *= 2
         m //= 2
     return a
@@ -174,13 +217,15 @@ def table1_sqnr(n: int, butterfly: str, trials: int = 200, seed: int = 0):
     return sqnr_db(ref, fp16_radix2_fft(x, butterfly))
 
 
-def table5_sqnr(n: int, fmt: str, trials: int = 200, seed: int = 0):
-    """Table V harness (storage rounding, double compute)."""
+def table5_sqnr(n: int, fmt: str, trials: int = 200, seed: int = 0, rounding: str = "rne",
+                feedback: bool = False):
+    """Table V harness (storage rounding, double compute), optionally with
+    stochastic rounding or error feedback."""
     rng = np.random.default_rng(seed)
     g = rng.standard_normal((2, trials, n))
     x = g[0] + 1j * g[1]
     ref = _oracle_fft(x)
-    return sqnr_db(ref, storage_fft(x, fmt))
+    return sqnr_db(ref, storage_fft(x, fmt, rounding=rounding, feedback=feedback, seed=seed + 1))
 
 
 def fp16_compress(x, H, bfp: bool = True, butterfly: str = "standard"):

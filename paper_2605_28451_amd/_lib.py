@@ -80,6 +80,8 @@ SIGNATURES = {
     "sar_azimuth_phase_grad": (_I, [_P, _P, _P, _P, _P, _P, _P, _I, _P]),
     "sar_autofocus_adam": (_I, [_P, _P, _P, _P, _P, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, _P]),
+    "sar_autofocus_adam_schedule": (_I, [_P, _P, _P, _P, _P, _I, _P, _I, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, _P]),
 }
 
 _lib = None

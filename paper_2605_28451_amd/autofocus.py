@@ -129,16 +129,29 @@ def entropy_and_grad(plan, rc_t, h_az, phase, img=None, stats=None, grad=None):
     return stats[2], grad, img
 
 
+def cosine_schedule(steps: int, lr_max: float = 2.5, lr_min: float = 0.02):
+    """lr_k = lr_min + (lr_max - lr_min) (1 + cos(pi (k - 1) / steps)) / 2, k = 1..steps:
+    large steps first (a phase error of several radians across the
+    aperture), small ones at the end."""
+    import math
+    return [lr_min + (lr_max - lr_min) * 0.5 * (1.0 + math.cos(math.pi * (k - 1) / steps))
+            for k in range(1, steps + 1)]
+
+
 class PhaseAdam:
     """Adam on a device phase vector (Kingma & Ba, 2015), moments and step
     count on the device (the library's sar_autofocus_adam), so the update
     needs no host round trip and can be captured in a graph."""
 
-    def __init__(self, phase, lr=0.3, betas=(0.9, 0.999), eps=1e-8):
+    def __init__(self, phase, lr=0.3, betas=(0.9, 0.999), eps=1e-8, lr_schedule=None):
         if phase.dtype != torch.float32 or not phase.is_cuda or not phase.is_contiguous():
             raise ValueError("phase: contiguous float32 device tensor")
         self.phase = phase
         self.lr, self.betas, self.eps = float(lr), (float(betas[0]), float(betas[1])), float(eps)
+        self.schedule = None
+        if lr_schedule is not None:
+            # step k uses lr_schedule[min(k, len) - 1], read on the device
+            self.schedule = torch.as_tensor(lr_schedule, dtype=torch.float32).to(phase.device).contiguous()
         self.m = torch.zeros_like(phase)
         self.v = torch.zeros_like(phase)
         self.count = torch.zeros(1, dtype=torch.int32, device=phase.device)
@@ -146,10 +159,17 @@ class PhaseAdam:
     def step(self, grad, stream=None):
         if grad.dtype != torch.float32 or grad.numel() != self.phase.numel() or not grad.is_cuda:
             raise ValueError("grad: float32 device tensor of the phase's size")
-        check(_lib.load().sar_autofocus_adam(_ptr(self.phase), _ptr(grad), _ptr(self.m), _ptr(self.v),
-                                             _ptr(self.count), self.phase.numel(), self.lr,
-                                             self.betas[0], self.betas[1], self.eps, _stream(stream)),
-              "sar_autofocus_adam")
+        lib = _lib.load()
+        if self.schedule is not None:
+            check(lib.sar_autofocus_adam_schedule(_ptr(self.phase), _ptr(grad), _ptr(self.m), _ptr(self.v),
+                                                  _ptr(self.count), self.phase.numel(), _ptr(self.schedule),
+                                                  self.schedule.numel(), self.betas[0], self.betas[1],
+                                                  self.eps, _stream(stream)), "sar_autofocus_adam_schedule")
+        else:
+            check(lib.sar_autofocus_adam(_ptr(self.phase), _ptr(grad), _ptr(self.m), _ptr(self.v),
+                                         _ptr(self.count), self.phase.numel(), self.lr,
+                                         self.betas[0], self.betas[1], self.eps, _stream(stream)),
+                  "sar_autofocus_adam")
 
 
 class AutofocusLoop:
@@ -158,11 +178,11 @@ class AutofocusLoop:
     current stream.  With graph=True the iteration is captured once in a HIP
     graph (buffers preallocated here) and each step() replays it."""
 
-    def __init__(self, plan, rc_t, h_az, phase, lr=0.3, graph=True):
+    def __init__(self, plan, rc_t, h_az, phase, lr=0.3, graph=True, lr_schedule=None):
         n = plan.n
         rows = rc_t.numel() // (2 * n)
         self.plan, self.rc_t, self.h_az, self.phase = plan, rc_t, h_az, phase
-        self.opt = PhaseAdam(phase, lr=lr)
+        self.opt = PhaseAdam(phase, lr=lr, lr_schedule=lr_schedule)
         self.img = torch.empty((rows, n, 2), dtype=torch.float32, device=rc_t.device)
         self.stats = torch.empty(3, dtype=torch.float64, device=rc_t.device)
         self.grad = torch.empty(n, dtype=torch.float32, device=rc_t.device)
@@ -178,7 +198,7 @@ class AutofocusLoop:
             with torch.cuda.stream(s):
                 entropy_and_grad(plan, rc_t, h_az, phase, img=self.img, stats=self.stats,
                                  grad=self.grad)
-                PhaseAdam(torch.zeros_like(phase), lr=lr).step(self.grad)
+                PhaseAdam(torch.zeros_like(phase), lr=lr, lr_schedule=lr_schedule).step(self.grad)
                 s.synchronize()
                 with torch.cuda.graph(g, stream=s):
                     self._iteration()

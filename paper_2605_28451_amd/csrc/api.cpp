@@ -206,7 +206,7 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   if (row_exp) a.flags |= bfp::KF_ADAPT;
   a.shift = shift;
   if (shift) a.flags |= bfp::KF_RAMP;
-  if (grid_used) *grid_used = bfp::rows_grid(p->log2n, rows, a.grid_limit);
+  a.grid_out = grid_used;
   const bool out32 = (eff & BFP_FLAG_OUT_FP32) != 0;
   int cur = 0;
   (void)hipGetDevice(&cur);
@@ -608,8 +608,23 @@ int sar_autofocus_adam(float *phase, const float *grad, float *m, float *v, unsi
   if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
     return fail(BFP_EINVAL, "beta1 and beta2 must lie in [0, 1)");
   if (!(eps > 0.0f && eps < 1e30f)) return fail(BFP_EINVAL, "eps must be finite and > 0");
-  hipError_t e = bfp::launch_adam(phase, grad, m, v, step, n, lr, beta1, beta2, eps,
+  hipError_t e = bfp::launch_adam(phase, grad, m, v, step, n, lr, beta1, beta2, eps, nullptr, 0,
                                   (hipStream_t)stream);
+  return e == hipSuccess ? BFP_OK : hip_fail(e, "Adam launch");
+}
+
+int sar_autofocus_adam_schedule(float *phase, const float *grad, float *m, float *v, unsigned *step,
+                                int n, const float *lr_schedule, int schedule_len, float beta1,
+                                float beta2, float eps, void *stream) {
+  if (n < 1 || n > (1 << 20)) return fail(BFP_EINVAL, "n outside [1, 2^20]");
+  if (!phase || !grad || !m || !v || !step || !lr_schedule) return fail(BFP_EINVAL, "NULL pointer");
+  if (schedule_len < 1 || schedule_len > (1 << 20))
+    return fail(BFP_EINVAL, "schedule_len outside [1, 2^20]");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+    return fail(BFP_EINVAL, "beta1 and beta2 must lie in [0, 1)");
+  if (!(eps > 0.0f && eps < 1e30f)) return fail(BFP_EINVAL, "eps must be finite and > 0");
+  hipError_t e = bfp::launch_adam(phase, grad, m, v, step, n, 0.0f, beta1, beta2, eps, lr_schedule,
+                                  schedule_len, (hipStream_t)stream);
   return e == hipSuccess ? BFP_OK : hip_fail(e, "Adam launch");
 }
 
@@ -637,6 +652,7 @@ int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, co
   a.partial = az_plan->pg_partial;
   a.grad = grad_phase;
   a.rows = n_range;
+  a.rows_per_thread = az_plan->tune_rr;
   e = bfp::launch_phase_grad(az_plan->prec == BFP_FP16_STORE_FP32_COMPUTE, az_plan->log2n, a,
                              stats != nullptr, (hipStream_t)stream);
   return e == hipSuccess ? BFP_OK : hip_fail(e, "phase gradient launch");

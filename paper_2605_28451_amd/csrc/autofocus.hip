@@ -175,12 +175,27 @@ hipError_t launch_entropy_grad(const void *img, const double *stats, const float
 // autofocus steps need no host round trip and can be replayed from a graph.
 // One workgroup: the counter is read once, and written back after every
 // element has used it.
+// lr_sched (device, sched_len values) replaces lr when given: step k uses
+// lr_sched[min(k, sched_len) - 1]; an entry that is not finite and >= 0
+// gives a zero step.
 __global__ void __launch_bounds__(1024) adam_kernel(float *phase, const float *grad, float *m, float *v,
                                                     unsigned *step, int n, float lr, float b1,
-                                                    float b2, float eps) {
+                                                    float b2, float eps, const float *lr_sched,
+                                                    int sched_len) {
   __shared__ unsigned k_s;
-  if (threadIdx.x == 0) k_s = step[0] + 1u;
+  __shared__ float lr_s;
+  if (threadIdx.x == 0) {
+    const unsigned k = step[0] + 1u;
+    k_s = k;
+    float l = lr;
+    if (lr_sched) {
+      l = lr_sched[(k < (unsigned)sched_len ? k : (unsigned)sched_len) - 1u];
+      if (!(l >= 0.0f && l < 1e30f)) l = 0.0f;
+    }
+    lr_s = l;
+  }
   __syncthreads();
+  lr = lr_s;
   // bias corrections 1 - beta^k, in FP64: near k = 1, 1 - beta^k is small
   // and an FP32 power's last-place error would be a large part of it
   const float c1 = (float)(1.0 - pow((double)b1, (double)k_s));
@@ -198,23 +213,31 @@ __global__ void __launch_bounds__(1024) adam_kernel(float *phase, const float *g
 }
 
 hipError_t launch_adam(float *phase, const float *grad, float *m, float *v, unsigned *step, int n,
-                       float lr, float b1, float b2, float eps, hipStream_t s) {
+                       float lr, float b1, float b2, float eps, const float *lr_sched, int sched_len,
+                       hipStream_t s) {
   hipLaunchKernelGGL(adam_kernel, dim3(1), dim3(1024), 0, s, phase, grad, m, v, step, n, lr, b1, b2,
-                     eps);
+                     eps, lr_sched, sched_len);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------ phase gradient ----
 
-template <class StoreT, int LOG2N, bool FUSED>
+// RR range rows per thread and iteration (Engine::run_rr: the rows share
+// the twiddles and the barriers of each LDS exchange); the per-pulse sums of
+// the RR rows go into the same registers, row by row in order.  NB LDS
+// buffers per row (2: one barrier per exchange).
+template <class StoreT, int LOG2N, bool FUSED, int RR, int NB>
 __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGradArgs a) {
   typedef Geometry<LOG2N> G;
   typedef Engine<ModeFP32, LOG2N> EN;
   constexpr int E = G::E, T = G::T, N = G::N;
-  __shared__ c32 lds_all[G::TPW * G::LDS_N];
+  constexpr int ROWS = G::TPW * RR;
+  __shared__ c32 lds_all[NB * ROWS * G::LDS_N];
   // one transform per workgroup for N >= 4096: keep the row index uniform
   const int local = G::TPW == 1 ? 0 : (int)(threadIdx.x / T);
-  c32 *lds = lds_all + local * G::LDS_N;
+  c32 *lds = lds_all + local * RR * G::LDS_N;
+  c32 *const buf[2] = {lds, lds + (NB == 2 ? ROWS * G::LDS_N : 0)};
+  unsigned xch = 0;
   const c32 *tw = static_cast<const c32 *>(a.tw32);
   const StoreT *flt = static_cast<const StoreT *>(a.filter);
   const c32 *ph = static_cast<const c32 *>(a.phasor);
@@ -228,47 +251,54 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
   float acc[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = 0.0f;
-  const int groups = (a.rows + G::TPW - 1) / G::TPW;
+  const int groups = (a.rows + ROWS - 1) / ROWS;
   for (int g = blockIdx.x; g < groups; g += gridDim.x) {
-    // the thread index, made opaque per row: otherwise the compiler hoists
+    // the thread index, made opaque per group: otherwise the compiler hoists
     // every pass's LDS and twiddle addresses out of the loop into registers
     // (the empty statement emits no instruction)
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int t = tid & (T - 1);
-    const long long row = (long long)g * G::TPW + local;
-    const bool active = row < a.rows;
     const unsigned ti = (unsigned)t;
-    c32 v[E];
-    if (active) {
-      load_row<G>(v, gin, row, ti);
-      if constexpr (FUSED) {
+    c32 v[RR][E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = entropy_grad_of(v[e], S, Ent, 1.0f);
+    for (int q = 0; q < RR; ++q) {
+      const long long row = (long long)g * ROWS + q * G::TPW + local;
+      if (row < a.rows) {
+        load_row<G>(v[q], gin, row, ti);
+        if constexpr (FUSED) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[q][e] = entropy_grad_of(v[q][e], S, Ent, 1.0f);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[q][e] = c32{0.0f, 0.0f};
       }
-    } else {
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = c32{0.0f, 0.0f};
     }
-    EN::run(v, lds, tw, t);
+    EN::template run_rr<false, RR, NB>(v, buf, xch, tw, t);
     {
       StoreT h[E];
       load_row<G, false>(h, flt, 0, ti);
 #pragma unroll
       for (int e = 0; e < E; ++e)  // adjoint: conj(H_a), then the block shift
-        v[e] = conj_pow2<LOG2N>(cmul(v[e], cconj(to_c32(h[e]))));
-    }
-    EN::run(v, lds, tw, t);
-    if (active) {
-      StoreT r[E];
-      c32 p[E];
-      load_row<G>(r, rc, row, ti);
-      load_row<G, false>(p, ph, 0, ti);
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const c32 gz = cconj(v[e]);
-        const c32 z = cmul(to_c32(r[e]), p[e]);
-        acc[e] += gz.y * z.x - gz.x * z.y;  // Im(gz conj z)
+        for (int q = 0; q < RR; ++q) v[q][e] = conj_pow2<LOG2N>(cmul(v[q][e], cconj(to_c32(h[e]))));
+    }
+    EN::template run_rr<false, RR, NB>(v, buf, xch, tw, t);
+    c32 p[E];
+    load_row<G, false>(p, ph, 0, ti);
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+      const long long row = (long long)g * ROWS + q * G::TPW + local;
+      if (row < a.rows) {
+        StoreT r[E];
+        load_row<G>(r, rc, row, ti);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const c32 gz = cconj(v[q][e]);
+          const c32 z = cmul(to_c32(r[e]), p[e]);
+          acc[e] += gz.y * z.x - gz.x * z.y;  // Im(gz conj z)
+        }
       }
     }
   }
@@ -302,13 +332,15 @@ __global__ void __launch_bounds__(256) partial_sum_kernel(const float *__restric
     out[(long long)blockIdx.y * n + m] = (float)(((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c]);
 }
 
-template <class StoreT, int LOG2N>
-static hipError_t launch_pg(const PhaseGradArgs &a, bool fused, int grid, hipStream_t s) {
+template <class StoreT, int LOG2N, int RR, int NB>
+static hipError_t launch_pg_rr(const PhaseGradArgs &a, bool fused, hipStream_t s) {
   typedef Geometry<LOG2N> G;
+  const int groups = (a.rows + G::TPW * RR - 1) / (G::TPW * RR);
+  const int grid = groups < kPhaseGradBlocks ? (groups < 1 ? 1 : groups) : kPhaseGradBlocks;
   if (fused)
-    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, true>), dim3(grid), dim3(G::WG), 0, s, a);
+    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, true, RR, NB>), dim3(grid), dim3(G::WG), 0, s, a);
   else
-    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, false>), dim3(grid), dim3(G::WG), 0, s, a);
+    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, false, RR, NB>), dim3(grid), dim3(G::WG), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = G::N;
@@ -323,12 +355,16 @@ static hipError_t launch_pg(const PhaseGradArgs &a, bool fused, int grid, hipStr
   return hipGetLastError();
 }
 
-int phase_grad_grid(int log2n, int rows) {
-  const int T = threads_per_transform(log2n);
-  const int wg = T < 256 ? 256 : T;
-  const int tpw = wg / T;
-  int groups = (rows + tpw - 1) / tpw;
-  return groups < kPhaseGradBlocks ? (groups < 1 ? 1 : groups) : kPhaseGradBlocks;
+// Two rows per iteration where the plan asks for it and their FP32 exchange
+// buffers leave LDS for two workgroups per CU (n <= 4096); one otherwise.
+template <class StoreT, int LOG2N>
+static hipError_t launch_pg(const PhaseGradArgs &a, bool fused, hipStream_t s) {
+  typedef Geometry<LOG2N> G;
+  constexpr long kSet2 = (long)G::TPW * 2 * G::LDS_N * sizeof(c32);
+  if constexpr (kSet2 <= 80 * 1024) {
+    if (a.rows_per_thread == 2) return launch_pg_rr<StoreT, LOG2N, 2, 1>(a, fused, s);
+  }
+  return launch_pg_rr<StoreT, LOG2N, 1, 1>(a, fused, s);
 }
 
 long long phase_grad_scratch_floats(int log2n) {
@@ -340,10 +376,9 @@ long long phase_grad_scratch_floats(int log2n) {
 
 hipError_t launch_phase_grad(bool fp16_storage, int log2n, const PhaseGradArgs &a, bool fused,
                              hipStream_t s) {
-  const int grid = phase_grad_grid(log2n, a.rows);
 #define BFP_PG_CASE(L)                                                              \
   case L:                                                                           \
-    return fp16_storage ? launch_pg<h2, L>(a, fused, grid, s) : launch_pg<c32, L>(a, fused, grid, s);
+    return fp16_storage ? launch_pg<h2, L>(a, fused, s) : launch_pg<c32, L>(a, fused, s);
   switch (log2n) {
     BFP_PG_CASE(8)
     BFP_PG_CASE(9)

@@ -95,13 +95,6 @@ int pass_count(int log2n) {
   geometry(log2n, e, p, r);
   return p;
 }
-int rows_grid(int log2n, int rows, int grid_limit) {
-  const int T = threads_per_transform(log2n);
-  const int tpw = (T < 256 ? 256 : T) / T;
-  int grid = (rows + tpw - 1) / tpw;
-  if (grid_limit > 0 && grid > grid_limit) grid = grid_limit;
-  return grid;
-}
 
 int threads_per_transform(int log2n) {
   switch (log2n) {

@@ -35,14 +35,13 @@ struct RowArgs {
   int grid_limit;        // > 0: persistent grid of at most this many workgroups
   int engine;            // 0: matrix cores where available, 1: vector ALU only
   int rows_per_thread;   // 1, or 2: the multi-row kernel where it covers the variant
+  int *grid_out;         // host: set to the launch's workgroup count, or NULL
   double *ent_partial;   // compression to FP32 with phasor: per-workgroup (S, Q) of the
-                         // output's entropy sums (see rows_grid), or NULL
+                         // output's entropy sums (one per workgroup: grid_out), or NULL
   int *row_exp;          // KF_ADAPT: per-row block exponent of the output, or NULL
   const float *shift;    // KF_RAMP: per-row range shift in bins (RCMC), or NULL
 };
 
-// Workgroups a row launch uses (what the per-workgroup partials count).
-int rows_grid(int log2n, int rows, int grid_limit);
 
 // whether (mode, size) has a matrix-core engine
 inline bool has_mfma_engine(int mode, int log2n) { return mode == 3 && log2n == 12; }
@@ -108,6 +107,7 @@ struct PhaseGradArgs {
   float *partial;        // kPhaseGradBlocks * transforms-per-workgroup rows of n floats
   float *grad;           // n floats out
   int rows;
+  int rows_per_thread;   // 1, or 2 where the kernel fits (n <= 4096)
 };
 // (S, Q, E) from `blocks` partial (S, Q) pairs, summed in a fixed order.
 hipError_t launch_entropy_final(const double *partial, int blocks, double *stats, hipStream_t s);
@@ -124,7 +124,8 @@ hipError_t launch_entropy_grad(const void *img, const double *stats, const float
 hipError_t launch_phase_grad(bool fp16_storage, int log2n, const PhaseGradArgs &a, bool fused,
                              hipStream_t s);
 hipError_t launch_adam(float *phase, const float *grad, float *m, float *v, unsigned *step, int n,
-                       float lr, float b1, float b2, float eps, hipStream_t s);
+                       float lr, float b1, float b2, float eps, const float *lr_sched, int sched_len,
+                       hipStream_t s);
 long long phase_grad_scratch_floats(int log2n);
 
 }  // namespace bfp

@@ -437,8 +437,12 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel_rr(RowArgs a) 
   constexpr int E = G::E, T = G::T, N = G::N;
   constexpr bool conj_f = (V & V_CONJ) != 0;
   constexpr bool phasor = (V & V_PHASOR) != 0;
-  static_assert((V & ~(V_CONJ | V_PHASOR)) == 0, "plain, conjugated-filter and phasor variants only");
+  constexpr bool ent = (V & V_ENT) != 0;
+  static_assert((V & ~(V_CONJ | V_PHASOR | V_ENT)) == 0, "plain, conjugated-filter, phasor and entropy variants only");
   static_assert(!phasor || OP == OP_COMPRESS, "the phasor belongs to the compression");
+  static_assert(!ent || (OP == OP_COMPRESS && OUT32 && !conj_f),
+                "entropy sums are a variant of the (phase-corrected) compression to FP32");
+  double es = 0.0, eq = 0.0;
   static_assert(!PIPE || (EN::kTwRegs && NB == 2), "the pipelined form keeps its twiddles in registers");
   __shared__ typename M::Lds lds_all[NB * G::TPW * RR * G::LDS_N];
   const int local = G::TPW == 1 ? 0 : (int)(threadIdx.x / T);
@@ -565,6 +569,16 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel_rr(RowArgs a) 
           c32 *dst = static_cast<c32 *>(a.out) + row * N + tt;
 #pragma unroll
           for (int e = 0; e < E; ++e) st_stream(dst + (unsigned)(T * e), to_c32(v[q][e]));
+          if constexpr (ent) {
+            // as in row_kernel: |I|^2 and |I|^2 ln |I|^2 in FP32, sums in FP64
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+              const c32 z = to_c32(v[q][e]);
+              const float p = z.x * z.x + z.y * z.y;
+              es += p;
+              eq += (double)p * (double)ln_pos(p);
+            }
+          }
         } else {
           Store *dst = static_cast<Store *>(a.out) + row * N + tt;
 #pragma unroll
@@ -580,6 +594,24 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel_rr(RowArgs a) 
       }
     }
     if (bad) atomicAdd(a.nonfinite, (unsigned long long)bad);
+  }
+  if constexpr (ent) {
+    // fixed-order tree over the workgroup; one (S, Q) per workgroup
+    __shared__ double esh[2][G::WG];
+    esh[0][threadIdx.x] = es;
+    esh[1][threadIdx.x] = eq;
+    __syncthreads();
+    for (int w = G::WG / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        esh[0][threadIdx.x] += esh[0][threadIdx.x + w];
+        esh[1][threadIdx.x] += esh[1][threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      a.ent_partial[2 * blockIdx.x] = esh[0][0];
+      a.ent_partial[2 * blockIdx.x + 1] = esh[1][0];
+    }
   }
 }
 
@@ -694,6 +726,7 @@ static hipError_t launch_mfma(const RowArgs &a, hipStream_t s) {
   if (a.rows <= 0) return hipSuccess;
   unsigned grid = (unsigned)a.rows;
   if (a.grid_limit > 0 && grid > (unsigned)a.grid_limit) grid = (unsigned)a.grid_limit;
+  if (a.grid_out) *a.grid_out = (int)grid;
   hipLaunchKernelGGL((row_kernel_mfma<OP, V, OUT32>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -704,6 +737,7 @@ static hipError_t launch_vector(const RowArgs &a, hipStream_t s) {
   typedef Geometry<LOG2N> G;
   unsigned grid = (unsigned)((a.rows + G::TPW - 1) / G::TPW);
   if (a.grid_limit > 0 && grid > (unsigned)a.grid_limit) grid = (unsigned)a.grid_limit;
+  if (a.grid_out) *a.grid_out = (int)grid;
   if constexpr (Engine<MODE, LOG2N>::kTwRegs) {
     if (a.grid_limit > 0) {
       hipLaunchKernelGGL((row_kernel<MODE, LOG2N, OP, V, OUT32, true>), dim3(grid), dim3(G::WG), 0, s, a);
@@ -719,7 +753,7 @@ static hipError_t launch_vector(const RowArgs &a, hipStream_t s) {
 template <int LOG2N, int OP, int V, bool OUT32>
 static bool launch_rr(const RowArgs &a, hipStream_t s, hipError_t &err) {
   typedef Geometry<LOG2N> G;
-  if constexpr ((V & ~(V_CONJ | V_PHASOR)) != 0 || ((V & V_PHASOR) && OP != OP_COMPRESS)) {
+  if constexpr ((V & ~(V_CONJ | V_PHASOR | V_ENT)) != 0 || ((V & V_PHASOR) && OP != OP_COMPRESS)) {
     return false;
   } else {
     constexpr int RR = 2;
@@ -734,6 +768,7 @@ static bool launch_rr(const RowArgs &a, hipStream_t s, hipError_t &err) {
       unsigned grid = (unsigned)((a.rows + G::TPW * RR - 1) / (G::TPW * RR));
       if (a.grid_limit > 0 && grid > (unsigned)a.grid_limit) grid = (unsigned)a.grid_limit;
       constexpr bool kPipe = Engine<MODE, LOG2N>::kTwRegs && NB == 2;
+      if (a.grid_out) *a.grid_out = (int)grid;
       if (kPipe && a.grid_limit > 0)
         hipLaunchKernelGGL((row_kernel_rr<MODE, LOG2N, OP, V, OUT32, RR, 2, kPipe>), dim3(grid), dim3(G::WG), 0, s, a);
       else

@@ -73,3 +73,36 @@ def test_fp16_emulator_is_exact_on_dc():
         assert y[0] == n and np.all(y[1:] == 0)
         a = emulator.fp16_radix2_fft(((-1.0) ** np.arange(n))[None], butterfly)[0]
         assert a[n // 2] == n and np.count_nonzero(a) == 1
+
+
+def test_stochastic_rounding_is_unbiased_and_brackets():
+    # each value rounds to one of its two neighbours in the format, with the
+    # neighbour's probability equal to the closeness: the mean over many draws
+    # is the value itself
+    rng = np.random.default_rng(3)
+    x = np.array([0.3, -1.7, 5.1e-3, 300.0, 1000.0, 0.0, 2.0])
+    for fmt in ("e4m3", "e5m2"):
+        r = np.stack([emulator.round_to_format_stochastic(x, fmt, rng.random(x.shape)) for _ in range(20000)])
+        ok = np.isclose(r, r.min(0)) | np.isclose(r, r.max(0))
+        assert ok.all()
+        inside = np.abs(x) < emulator.FORMATS[fmt][2]
+        np.testing.assert_allclose(r.mean(0)[inside], x[inside], rtol=2e-2, atol=1e-6)
+        assert np.all(np.abs(r[:, ~inside]) == emulator.FORMATS[fmt][2])  # saturation
+        assert np.all(r[:, x == 2.0] == 2.0) and np.all(r[:, x == 0.0] == 0.0)  # exact stays exact
+
+
+@pytest.mark.parametrize("fmt", ["e4m3", "e5m2"])
+def test_fp8_precision_recovery_does_not_lift_the_floor_at_equal_bytes(fmt):
+    # Sec. VII / VIII name stochastic rounding and error feedback as ways past
+    # the FP8 floor.  In Table V's harness (N = 1024): stochastic rounding
+    # doubles the variance of each rounding (about 3 dB worse than RNE);
+    # error feedback (the residual kept in a second FP8 value) gains more
+    # than 25 dB but spends FP16's bytes and stays well below FP16 storage
+    n, trials = 1024, 40
+    rne = emulator.table5_sqnr(n, fmt, trials=trials)
+    sr = emulator.table5_sqnr(n, fmt, trials=trials, rounding="stochastic")
+    ef = emulator.table5_sqnr(n, fmt, trials=trials, feedback=True)
+    fp16 = emulator.table5_sqnr(n, "fp16", trials=trials)
+    assert 1.5 <= rne - sr <= 4.5, (rne, sr)
+    assert ef - rne >= 25.0, (ef, rne)
+    assert fp16 - ef >= 8.0, (fp16, ef)
