@@ -29,8 +29,20 @@ sys.path.insert(0, ROOT)
 METRIC = "FP16-BFP FFT GFLOP/s (5N·log2N) + SAR frames/s at stated SQNR vs FP32 path"
 # headline precision mode and the kernel that carries it
 HEAD_MODE = "fp16"
-HEAD_KERNEL = ("row_kernel<ModeFP16, 12, OP_COMPRESS, V_PLAIN, false, PIPE> (rows.hip): "
-               "pipelined persistent grid, 3 workgroups per CU")
+RADIX_PLANS_4096 = {0: "16 16 16, 16 values per thread", 1: "8 8 8 8, 8 values per thread"}
+
+
+def head_kernel_text(t):
+    """The headline kernel the autotuner chose (rows.hip)."""
+    if t is None:
+        return "row_kernel (rows.hip), default tuning"
+    name = "row_kernel_rr" if (t["rows_per_thread"] > 1 or t["radix_plan"] == 1) else "row_kernel"
+    grid = ("one workgroup per row group" if t["blocks_per_cu"] == 0 else
+            "the default grid" if t["blocks_per_cu"] < 0 else
+            f"a persistent grid of {t['blocks_per_cu']} workgroups per CU")
+    return (f"{name}<ModeFP16, 12, OP_COMPRESS, V_PLAIN> (rows.hip), {t['engine']}, radix plan "
+            f"{t['radix_plan']} ({RADIX_PLANS_4096[t['radix_plan']]}), {t['rows_per_thread']} row(s) per "
+            f"thread, {grid}; chosen by the library autotuner on the rotating buffers")
 MODE_TEXT = {
     "fp16": "pure FP16 (packed half2 arithmetic, FP16 LDS and twiddles)",
     "fp16_mul_fp32_acc": "FP16 multiply / FP32 accumulate (radix-16 butterflies on the matrix cores)",
@@ -174,9 +186,17 @@ def rotating_sets(make, n_sets):
     return [make(i) for i in range(n_sets)]
 
 
-def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30, adaptive=False):
+def tuning_record(plan, ms):
+    e, b, rr, pl = plan.get_tuning_ex()
+    return {"engine": "matrix cores" if e == 0 else "vector ALU", "blocks_per_cu": b,
+            "rows_per_thread": rr, "radix_plan": pl, "tuned_ms": round(ms, 5)}
+
+
+def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30, adaptive=False, tune=True):
     """Fused range compression in `mode`, rotating buffers totalling >= min_bytes
-    (adaptive: the per-row adaptive block shift, with its exponent rows)."""
+    (adaptive: the per-row adaptive block shift, with its exponent rows).
+    tune: the library's autotuner picks engine, grid, rows per thread and
+    radix plan on the same rotating buffers before the timed steps."""
     import torch
     from paper_2605_28451_amd import api, scenes
     sc = scenes.range_scene(seed=2, n_pulses=rows, n=n)
@@ -190,6 +210,7 @@ def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30, adaptive=Fal
     H = api.filter_tensor(sc.replica, n, mode)
 
     exps = [torch.empty(rows, dtype=torch.int32, device="cuda") for _ in range(n_sets)]
+    tuning = tuning_record(plan, plan.autotune_on(2, ins, outs, H, reps=10)) if tune and not adaptive else None
 
     def launch(i):
         if adaptive:
@@ -204,6 +225,7 @@ def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30, adaptive=Fal
         "ms_per_launch": ms,
         "ms_total": total,
         "bytes_per_launch": set_bytes,
+        "tuning": tuning,
     }
     res["gflops"] = fft_flops(n, 2 * rows) / (res["ms_per_launch"] * 1e-3) / 1e9
     res["hbm_gbs"] = set_bytes / (res["ms_per_launch"] * 1e-3) / 1e9
@@ -219,7 +241,7 @@ def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30, adaptive=Fal
     return res
 
 
-def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30, inverse=False):
+def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30, inverse=False, tune=True):
     import torch
     from paper_2605_28451_amd import api, scenes
     fmt = api.storage_format(mode)
@@ -230,13 +252,14 @@ def bench_fft(mode, rows, n, steps, warmup, min_bytes=1 << 30, inverse=False):
     ins = [x0 if i == 0 else x0.clone() for i in range(n_sets)]
     outs = [torch.empty_like(x0) for _ in range(n_sets)]
     plan = api.FFTPlan(n, rows, mode)
+    tuning = tuning_record(plan, plan.autotune_on(1 if inverse else 0, ins, outs, reps=10)) if tune else None
     if inverse:
         launch = lambda i: plan.inverse_bfp(ins[i], out=outs[i])  # noqa: E731
     else:
         launch = lambda i: plan.forward(ins[i], out=outs[i])  # noqa: E731
     ms, total = time_launches(launch, n_sets, steps, warmup)
     res = {"mode": mode, "op": "inverse_bfp" if inverse else "forward", "rows": rows, "n": n,
-           "buffer_sets": n_sets, "ms_per_launch": ms,
+           "buffer_sets": n_sets, "ms_per_launch": ms, "tuning": tuning,
            "gflops": fft_flops(n, rows) / (ms * 1e-3) / 1e9,
            "hbm_gbs": set_bytes / (ms * 1e-3) / 1e9}
     res["hbm_frac"] = res["hbm_gbs"] / HBM_PEAK_GBS
@@ -275,7 +298,7 @@ def frame_vs_oracle(sc, mode, img, pts):
             "max_abs_delta_irw_samples": _finite_or_none(max(d["irw_range"], d["irw_azimuth"]), 4)}
 
 
-def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False, streams=1):
+def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False, streams=1, tune=True):
     """Full 4096x4096 range-Doppler frame: fused range compression, LDS-tiled
     corner turn, fused azimuth compression (fused_ct: the corner turn folded
     into the range compression's store, no separate pass).  n_frames
@@ -308,9 +331,19 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
             api.corner_turn(rcs[i], fmt, out=rcts[i])
         aplan.azimuth_compress(rcts[i], Ha, out=imgs[i])
 
-    for i in range(warmup):
+    for i in range(max(warmup, n_frames)):
         frame(i % n_frames)
     torch.cuda.synchronize()
+    tuning = None
+    if tune and not fused_ct:
+        # both compressions tuned on the frame's own rotating buffers (the
+        # transposed store keeps its default grid)
+        tr = tuning_record(rplan, rplan.autotune_on(2, echoes, rcs, Hr, reps=5))
+        ta = tuning_record(aplan, aplan.autotune_on(2, rcts, imgs, Ha, reps=5))
+        tuning = {"range": tr, "azimuth": ta}
+        for i in range(n_frames):
+            frame(i)
+        torch.cuda.synchronize()
     reps = max(1, steps // n_frames)
     if graph:
         s = torch.cuda.Stream()
@@ -349,7 +382,7 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
            "hbm_gbs": bytes_frame / (ms * 1e-3) / 1e9, "bytes_per_frame": bytes_frame,
            "gflops": fft_flops(n, 4 * n) / (ms * 1e-3) / 1e9, "graph": graph,
            "frames_rotating": n_frames, "corner_turn": "fused into the range store" if fused_ct
-           else "separate LDS-tiled pass", "concurrent_streams": streams}
+           else "separate LDS-tiled pass", "concurrent_streams": streams, "tuning": tuning}
     torch.cuda.synchronize()
     res["_img"] = api.to_host(imgs[0], fmt)
     res["_scene"] = sc
@@ -840,6 +873,7 @@ def main():
             "precision": MODE_TEXT[HEAD_MODE],
             "buffer_sets": head["buffer_sets"],
             "working_set_mib": head["working_set_mib"],
+            "tuning": head["tuning"],
             "flop_convention": "5 N log2 N per transform, 2 transforms per pulse",
         },
         "roofline": {
@@ -849,7 +883,7 @@ def main():
             "unit": "GB/s",
             "frac": round(head["hbm_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(HEAD_MODE),
-            "kernel": HEAD_KERNEL,
+            "kernel": head_kernel_text(head["tuning"]),
             "algorithmic_bytes_per_launch": head["bytes_per_launch"],
         },
     }
@@ -872,7 +906,7 @@ def main():
             log(f"range compression mode={mode}")
             r = bench_compress(mode, rows, n, args.steps, args.warmup)
             modes[mode] = {"gflops": round(r["gflops"], 1), "hbm_gbs": round(r["hbm_gbs"], 1),
-                           "ms_per_launch": round(r["ms_per_launch"], 5)}
+                           "ms_per_launch": round(r["ms_per_launch"], 5), "tuning": r["tuning"]}
         out["range_compress_modes"] = modes
         out["fp16_over_fp32"] = round(head["gflops"] / modes["fp32"]["gflops"], 3)
         fft = {}
@@ -894,7 +928,8 @@ def main():
                 r = bench_fft("fp16", (1 << 25) // nn, nn, args.steps, args.warmup, inverse=inv)
                 by_n[f"{nn}_{'inverse_bfp' if inv else 'forward'}"] = {
                     "rows": r["rows"], "us_per_launch": round(r["ms_per_launch"] * 1e3, 2),
-                    "gflops": round(r["gflops"], 1), "hbm_frac": round(r["hbm_frac"], 4)}
+                    "gflops": round(r["gflops"], 1), "hbm_frac": round(r["hbm_frac"], 4),
+                    "tuning": r["tuning"]}
         out["fft_fp16_by_n"] = by_n
         log("plain forward FFT n=4096 batch=64 (latency-bound shape)")
         r = bench_fft("fp16", 64, n, args.steps, args.warmup, min_bytes=0)

@@ -168,28 +168,39 @@ int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *fi
 int fft_plan_set_tuning(bfp_plan p, int engine, int blocks_per_cu);
 int fft_plan_get_tuning(bfp_plan p, int *engine, int *blocks_per_cu);
 
-/* All tuning knobs: engine and blocks_per_cu as above, and rows_per_thread
+/* All tuning knobs: engine and blocks_per_cu as above, radix_plan and
+ * rows_per_thread.  radix_plan (0 or 1, sizes 32..16384; n <= 16 has one
+ * plan): the factorisation of n into radix passes, 0 the default (radix-16
+ * passes where they fit), 1 the second plan (radix-8 passes with 8 values
+ * per thread from 32 to 4096 points except 512, which takes 16 16 2; 16 16
+ * 8 4 at 8192; 4 16 16 16 at 16384).  The plan changes the order of the
+ * arithmetic, hence the rounding (both stay within the same accuracy); it
+ * applies to the variants rows_per_thread covers (below), with storage-type
+ * output, and the others run plan 0.  rows_per_thread
  * (1 or 2): with 2, the forward transform, the BFP inverse (with a filter,
  * its conjugate or none) and the compression (with a filter, its conjugate,
  * or a phase applied before the chain) transform two rows per thread
  * together, sharing twiddles and one barrier per LDS exchange; the other
  * variants, the matrix-core engine and sizes whose two rows would not leave
  * LDS for two workgroups per CU (FP32 exchanges above 4096 points, FP16
- * above 8192) ignore it.  Results are the same bits for every setting.
- * Uneven plans take rows_per_thread = 1.  A new plan has {1, -1, 2} in the
- * modes with FP32 arithmetic (BFP_FP32, BFP_FP16_STORE_FP32_COMPUTE and the
- * FP8-storage modes) and {1, -1, 1} in BFP_FP16 and BFP_FP16_MUL_FP32_ACC.
- * Errors: BFP_EINVAL. */
+ * above 8192) ignore it.  For one radix plan, results are the same bits for
+ * every engine-independent setting (blocks_per_cu, rows_per_thread).
+ * Uneven plans take rows_per_thread = 1 and radix_plan = 0.  A new plan has
+ * {1, -1, 2, 0} in the modes with FP32 arithmetic (BFP_FP32,
+ * BFP_FP16_STORE_FP32_COMPUTE and the FP8-storage modes) and {1, -1, 1, 0}
+ * in BFP_FP16 and BFP_FP16_MUL_FP32_ACC.  Errors: BFP_EINVAL. */
 typedef struct {
   int engine;
   int blocks_per_cu;
   int rows_per_thread;
+  int radix_plan;
 } bfp_tuning;
 int fft_plan_set_tuning_ex(bfp_plan p, const bfp_tuning *t);
 int fft_plan_get_tuning_ex(bfp_plan p, bfp_tuning *t);
 
 /* Times every tuning candidate of the plan (engine x blocks_per_cu x
- * rows_per_thread for rows plans, blocks_per_cu for uneven plans) on the
+ * rows_per_thread x radix_plan for rows plans, blocks_per_cu for uneven
+ * plans) on the
  * caller's buffers (op: 0
  * forward, 1 BFP inverse with `filter` (may be NULL), 2 fused compression
  * with `filter`; ignored for uneven plans), `reps` calls each after two
@@ -198,6 +209,12 @@ int fft_plan_get_tuning_ex(bfp_plan p, bfp_tuning *t);
  * `stream`. */
 int fft_autotune(bfp_plan p, int op, const void *in, void *out, const void *filter, int reps,
                  float *best_ms, void *stream);
+/* fft_autotune over n_sets buffer pairs, call k using (host arrays of device
+ * pointers) ins[k % n_sets] and outs[k % n_sets]: with sets that together
+ * exceed the last-level cache (256 MB on MI355X) every candidate is timed
+ * streaming from HBM, as it will run.  n_sets in [1, 4096]. */
+int fft_autotune_sets(bfp_plan p, int op, const void *const *ins, void *const *outs, int n_sets,
+                      const void *filter, int reps, float *best_ms, void *stream);
 
 /* Reads and clears the plan's non-finite counter; synchronises `stream`. */
 int fft_plan_nonfinite(bfp_plan p, void *stream, unsigned long long *count);

@@ -59,6 +59,7 @@ SIGNATURES = {
     "fft_plan_set_tuning_ex": (_I, [_P, _P]),
     "fft_plan_get_tuning_ex": (_I, [_P, _P]),
     "fft_autotune": (_I, [_P, _I, _P, _P, _P, _I, ctypes.POINTER(ctypes.c_float), _P]),
+    "fft_autotune_sets": (_I, [_P, _I, _P, _P, _I, _P, _I, ctypes.POINTER(ctypes.c_float), _P]),
     "fft_plan_uneven": (_I, [ctypes.POINTER(_P), _I, _P, _P, _I, _U]),
     "fft_uneven_offsets": (_I, [_P, ctypes.POINTER(_LL)]),
     "fft_uneven_total": (_I, [_P, ctypes.POINTER(_LL)]),

@@ -125,7 +125,7 @@ def corner_turn(x, fmt: str, out=None, stream=None):
 class Tuning(ctypes.Structure):
     """bfp_tuning: the knobs of fft_plan_set_tuning_ex."""
     _fields_ = [("engine", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
-                ("rows_per_thread", ctypes.c_int)]
+                ("rows_per_thread", ctypes.c_int), ("radix_plan", ctypes.c_int)]
 
 
 class FFTPlan:
@@ -260,20 +260,33 @@ class FFTPlan:
               "fft_plan_get_tuning")
         return int(e.value), int(b.value)
 
-    def set_tuning_ex(self, engine: int = 1, blocks_per_cu: int = -1, rows_per_thread: int = 1):
-        t = Tuning(int(engine), int(blocks_per_cu), int(rows_per_thread))
+    def set_tuning_ex(self, engine: int = 1, blocks_per_cu: int = -1, rows_per_thread: int = 1,
+                      radix_plan: int = 0):
+        t = Tuning(int(engine), int(blocks_per_cu), int(rows_per_thread), int(radix_plan))
         check(_lib.load().fft_plan_set_tuning_ex(self._h, ctypes.byref(t)), "fft_plan_set_tuning_ex")
 
     def get_tuning_ex(self):
+        """(engine, blocks_per_cu, rows_per_thread, radix_plan)"""
         t = Tuning()
         check(_lib.load().fft_plan_get_tuning_ex(self._h, ctypes.byref(t)), "fft_plan_get_tuning_ex")
-        return int(t.engine), int(t.blocks_per_cu), int(t.rows_per_thread)
+        return int(t.engine), int(t.blocks_per_cu), int(t.rows_per_thread), int(t.radix_plan)
 
     def autotune_on(self, op: int, x, out, filt=None, reps: int = 20, stream=None) -> float:
-        """Time every tuning candidate on (x, out), keep the fastest; returns ms/call."""
+        """Time every tuning candidate on (x, out), keep the fastest; returns ms/call.
+        x and out may also be equal-length lists of tensors: the calls then
+        rotate over the pairs (sets larger than the last-level cache time
+        every candidate from HBM)."""
         ms = ctypes.c_float()
-        check(_lib.load().fft_autotune(self._h, int(op), _ptr(x), _ptr(out), _ptr(filt), int(reps),
-                                       ctypes.byref(ms), _stream(stream)), "fft_autotune")
+        if isinstance(x, (list, tuple)):
+            if len(x) != len(out) or not x:
+                raise ValueError("x and out: lists of the same nonzero length")
+            ins = (ctypes.c_void_p * len(x))(*[t.data_ptr() for t in x])
+            outs = (ctypes.c_void_p * len(out))(*[t.data_ptr() for t in out])
+            check(_lib.load().fft_autotune_sets(self._h, int(op), ins, outs, len(x), _ptr(filt), int(reps),
+                                                ctypes.byref(ms), _stream(stream)), "fft_autotune_sets")
+        else:
+            check(_lib.load().fft_autotune(self._h, int(op), _ptr(x), _ptr(out), _ptr(filt), int(reps),
+                                           ctypes.byref(ms), _stream(stream)), "fft_autotune")
         return float(ms.value)
 
     def nonfinite(self, stream=None) -> int:
@@ -340,11 +353,27 @@ class UnevenPlan:
               "fft_plan_get_tuning")
         return int(e.value), int(b.value)
 
+    def set_tuning_ex(self, engine: int = 0, blocks_per_cu: int = 0, rows_per_thread: int = 1,
+                      radix_plan: int = 0):
+        t = Tuning(int(engine), int(blocks_per_cu), int(rows_per_thread), int(radix_plan))
+        check(_lib.load().fft_plan_set_tuning_ex(self._h, ctypes.byref(t)), "fft_plan_set_tuning_ex")
+
     def autotune_on(self, op: int, x, out, filt=None, reps: int = 20, stream=None) -> float:
-        """Time every tuning candidate on (x, out), keep the fastest; returns ms/call."""
+        """Time every tuning candidate on (x, out), keep the fastest; returns ms/call.
+        x and out may also be equal-length lists of tensors: the calls then
+        rotate over the pairs (sets larger than the last-level cache time
+        every candidate from HBM)."""
         ms = ctypes.c_float()
-        check(_lib.load().fft_autotune(self._h, int(op), _ptr(x), _ptr(out), _ptr(filt), int(reps),
-                                       ctypes.byref(ms), _stream(stream)), "fft_autotune")
+        if isinstance(x, (list, tuple)):
+            if len(x) != len(out) or not x:
+                raise ValueError("x and out: lists of the same nonzero length")
+            ins = (ctypes.c_void_p * len(x))(*[t.data_ptr() for t in x])
+            outs = (ctypes.c_void_p * len(out))(*[t.data_ptr() for t in out])
+            check(_lib.load().fft_autotune_sets(self._h, int(op), ins, outs, len(x), _ptr(filt), int(reps),
+                                                ctypes.byref(ms), _stream(stream)), "fft_autotune_sets")
+        else:
+            check(_lib.load().fft_autotune(self._h, int(op), _ptr(x), _ptr(out), _ptr(filt), int(reps),
+                                           ctypes.byref(ms), _stream(stream)), "fft_autotune")
         return float(ms.value)
 
     def execute(self, x, out=None, stream=None):

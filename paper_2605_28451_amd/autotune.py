@@ -1,7 +1,8 @@
 """Autotuner driver with a JSON cache.
 
 The timing loop runs in the library (fft_autotune: every candidate of the
-plan's tuning space -- engine, persistent-grid size and rows per thread --
+plan's tuning space -- engine, persistent-grid size, rows per thread and
+radix plan --
 timed with HIP events on the caller's buffers); this module keys the winners by device
 architecture, size, precision, operation and batch bucket and stores them in
 ``$BFP_AUTOTUNE_CACHE`` (default ``~/.cache/bfpfft/autotune.json``), so later
@@ -56,7 +57,8 @@ def apply_cached(plan, op: str = "forward") -> bool:
 
 def _apply(plan, entry):
     if hasattr(plan, "set_tuning_ex"):
-        plan.set_tuning_ex(entry["engine"], entry["blocks_per_cu"], entry.get("rows_per_thread", 1))
+        plan.set_tuning_ex(entry["engine"], entry["blocks_per_cu"], entry.get("rows_per_thread", 1),
+                           entry.get("radix_plan", 0))
     else:
         plan.set_tuning(entry["engine"], entry["blocks_per_cu"])
 
@@ -70,9 +72,9 @@ def tune(plan, op: str, x, out, filt=None, reps: int = 20, force: bool = False) 
         return d[k]
     ms = plan.autotune_on(OPS.get(op, 0), x, out, filt, reps)
     if hasattr(plan, "get_tuning_ex"):
-        e, b, rr = plan.get_tuning_ex()
+        e, b, rr, pl = plan.get_tuning_ex()
     else:
-        (e, b), rr = plan.get_tuning(), 1
-    d[k] = {"engine": e, "blocks_per_cu": b, "rows_per_thread": rr, "ms": ms}
+        (e, b), rr, pl = plan.get_tuning(), 1, 0
+    d[k] = {"engine": e, "blocks_per_cu": b, "rows_per_thread": rr, "radix_plan": pl, "ms": ms}
     _save(d)
     return d[k]

@@ -87,18 +87,20 @@ int log2_exact(long long n) {
 
 namespace {
 
-int upload_twiddles(int log2n, int prec, void **out) {
+// The twiddle table of radix plan `plan` (the matrix-core operands first
+// where the mode and size have that engine, plan 0 only).
+int upload_twiddles(int log2n, int prec, int plan, void **out) {
   int rad[4];
-  const int passes = bfp::pass_count(log2n);
-  for (int p = 0; p < 4; ++p) rad[p] = bfp::pass_radix(log2n, p);
+  const int passes = bfp::pass_count(log2n, plan);
+  for (int p = 0; p < 4; ++p) rad[p] = bfp::pass_radix(log2n, plan, p);
   std::vector<std::complex<double>> t = bfp::twiddle_table(log2n, rad, passes);
-  if ((int)t.size() != bfp::twiddle_entries(log2n))
+  if ((int)t.size() != bfp::twiddle_entries(log2n, plan))
     return fail(BFP_EINVAL, "internal: twiddle table size mismatch");
   const int fmt = tw_format(prec);
   size_t bytes = std::max<size_t>(16, t.size() * bfp_format_bytes(fmt));
   std::vector<unsigned char> host(bytes, 0);
   bfp::encode_complex(t.data(), t.size(), fmt, host.data());
-  if (bfp::has_mfma_engine(prec, log2n)) {
+  if (plan == 0 && bfp::has_mfma_engine(prec, log2n)) {
     // matrix-core table (DFT16 operands + dot2-form twiddles) first, the
     // vector-ALU engine's table after it at kMfmaTableBytes
     std::vector<uint16_t> m = bfp::mfma4096_table();
@@ -142,6 +144,7 @@ void free_plan(bfp_plan p) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(p->device);
   (void)hipFree(p->tw);
+  (void)hipFree(p->tw_alt);
   (void)hipFree(p->nonfinite);
   (void)hipFree(p->phasor);
   (void)hipFree(p->items);
@@ -191,6 +194,8 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   a.out = out;
   a.rows = rows;
   a.tw = p->tw;  // the launcher picks the engine's part of a two-engine table
+  a.tw_alt = p->tw_alt;
+  a.radix_plan = p->tune_plan;
   a.filter = filter;
   a.phasor = phasor;
   unsigned eff = flags | p->flags;
@@ -309,7 +314,8 @@ int fft_plan(bfp_plan *out, int n, int batch, int prec, unsigned flags) {
   p->tune_engine = 1;
   p->tune_bpc = kAutoBpc;
   p->tune_rr = default_rows_per_thread(prec);
-  st = upload_twiddles(l, prec, &p->tw);
+  st = upload_twiddles(l, prec, 0, &p->tw);
+  if (!st && bfp::second_plan(l)) st = upload_twiddles(l, prec, 1, &p->tw_alt);
   if (st) {
     free_plan(p);
     return st;
@@ -679,9 +685,13 @@ int fft_plan_set_tuning_ex(bfp_plan p, const bfp_tuning *t) {
     return fail(BFP_EINVAL, "rows_per_thread must be 1 or 2");
   if (p->kind == 1 && t->rows_per_thread != 1)
     return fail(BFP_EINVAL, "uneven plans take rows_per_thread = 1");
+  if (t->radix_plan < 0 || t->radix_plan > 1) return fail(BFP_EINVAL, "radix_plan must be 0 or 1");
+  if (t->radix_plan == 1 && (p->kind != 0 || !bfp::second_plan(p->log2n)))
+    return fail(BFP_EINVAL, "this plan's size has one radix plan (n <= 16, or an uneven plan)");
   int st = fft_plan_set_tuning(p, t->engine, t->blocks_per_cu);
   if (st) return st;
   p->tune_rr = t->rows_per_thread;
+  p->tune_plan = t->radix_plan;
   return BFP_OK;
 }
 
@@ -690,6 +700,7 @@ int fft_plan_get_tuning_ex(bfp_plan p, bfp_tuning *t) {
   t->engine = p->tune_engine;
   t->blocks_per_cu = p->tune_bpc;
   t->rows_per_thread = p->tune_rr;
+  t->radix_plan = p->tune_plan;
   return BFP_OK;
 }
 
@@ -700,28 +711,36 @@ int fft_plan_get_tuning(bfp_plan p, int *engine, int *blocks_per_cu) {
   return BFP_OK;
 }
 
-int fft_autotune(bfp_plan p, int op, const void *in, void *out, const void *filter, int reps,
-                 float *best_ms, void *stream) {
+int fft_autotune_sets(bfp_plan p, int op, const void *const *ins, void *const *outs, int n_sets,
+                      const void *filter, int reps, float *best_ms, void *stream) {
   if (!p) return fail(BFP_EINVAL, "plan is NULL");
   if (reps < 1 || reps > 10000) return fail(BFP_EINVAL, "reps must be in [1, 10000]");
+  if (n_sets < 1 || n_sets > 4096) return fail(BFP_EINVAL, "n_sets must be in [1, 4096]");
+  if (!ins || !outs) return fail(BFP_EINVAL, "NULL buffer array");
+  for (int i = 0; i < n_sets; ++i)
+    if (!ins[i] || !outs[i]) return fail(BFP_EINVAL, "NULL buffer in the sets");
   if (p->kind == 0 && (op < 0 || op > 2)) return fail(BFP_EINVAL, "op must be 0, 1 or 2");
   if (p->kind == 0 && op == 2 && !filter) return fail(BFP_EINVAL, "compression needs a filter");
   std::vector<bfp_tuning> cands;
   if (p->kind == 1) {
-    for (int b = 1; b <= p->uneven_max_bpc; ++b) cands.push_back({0, b, 1});
+    for (int b = 1; b <= p->uneven_max_bpc; ++b) cands.push_back({0, b, 1, 0});
   } else {
-    // engine x persistent grid x rows per thread (the matrix-core kernels
-    // take one row per workgroup)
+    // engine x persistent grid x rows per thread x radix plan (the
+    // matrix-core kernels take one row per workgroup and plan 0)
     const bool mf = bfp::has_mfma_engine(p->prec, p->log2n);
+    const int plans = bfp::second_plan(p->log2n) ? 2 : 1;
     for (int e = 0; e <= (mf ? 1 : 0); ++e)
       for (int b : {kAutoBpc, 0, 1, 2, 3, 4, 5, 6, 8})
-        for (int rr = 1; rr <= ((mf && e == 0) ? 1 : 2); ++rr) cands.push_back({mf ? e : 1, b, rr});
+        for (int rr = 1; rr <= ((mf && e == 0) ? 1 : 2); ++rr)
+          for (int pl = 0; pl < ((mf && e == 0) ? 1 : plans); ++pl) cands.push_back({mf ? e : 1, b, rr, pl});
   }
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(BFP_EHIP, "hipEventCreate failed");
-  auto call = [&]() -> int {
+  auto call = [&](int k) -> int {
+    const void *in = ins[k % n_sets];
+    void *out = outs[k % n_sets];
     if (p->kind == 1) return fft_exec_uneven(p, in, out, stream);
     if (op == 0) return fft_exec_fwd(p, in, out, stream);
     if (op == 1) return fft_exec_inv_bfp(p, in, out, filter, stream);
@@ -732,10 +751,10 @@ int fft_autotune(bfp_plan p, int op, const void *in, void *out, const void *filt
   int st = BFP_OK;
   for (auto &c : cands) {
     if ((st = fft_plan_set_tuning_ex(p, &c))) break;
-    for (int w = 0; w < 2 && !st; ++w) st = call();
+    for (int w = 0; w < 2 && !st; ++w) st = call(w);
     if (st) break;
     (void)hipEventRecord(e0, s);
-    for (int r = 0; r < reps && !st; ++r) st = call();
+    for (int r = 0; r < reps && !st; ++r) st = call(r);
     (void)hipEventRecord(e1, s);
     if (st) break;
     if (hipEventSynchronize(e1) != hipSuccess) { st = fail(BFP_EHIP, "hipEventSynchronize"); break; }
@@ -749,6 +768,14 @@ int fft_autotune(bfp_plan p, int op, const void *in, void *out, const void *filt
   if (st) return st;
   if (best_ms) *best_ms = best;
   return fft_plan_set_tuning_ex(p, &pick);
+}
+
+int fft_autotune(bfp_plan p, int op, const void *in, void *out, const void *filter, int reps,
+                 float *best_ms, void *stream) {
+  const void *ins[1] = {in};
+  void *outs[1] = {out};
+  if (!in || !out) return fail(BFP_EINVAL, "NULL data pointer");
+  return fft_autotune_sets(p, op, ins, outs, 1, filter, reps, best_ms, stream);
 }
 
 /* uneven entry points are defined in uneven_api.cpp */

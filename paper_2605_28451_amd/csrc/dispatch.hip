@@ -59,42 +59,49 @@ int uneven_blocks_per_cu(int mode) {
   return 1;
 }
 
-template <int L>
+template <int L, int PLAN>
 static void geo(int &entries, int &passes, int *rad) {
-  typedef Geometry<L> G;
+  typedef Geometry<L, PLAN> G;
   entries = G::tw_entries();
   passes = G::S::P;
   for (int p = 0; p < 4; ++p) rad[p] = G::radix(p);
 }
 
-static void geometry(int log2n, int &entries, int &passes, int *rad) {
+template <int PLAN>
+static void geometry_plan(int log2n, int &entries, int &passes, int *rad) {
   switch (log2n) {
-    case 3: geo<3>(entries, passes, rad); return;
-    case 4: geo<4>(entries, passes, rad); return;
-    case 5: geo<5>(entries, passes, rad); return;
-    case 6: geo<6>(entries, passes, rad); return;
-    case 7: geo<7>(entries, passes, rad); return;
-    case 8: geo<8>(entries, passes, rad); return;
-    case 9: geo<9>(entries, passes, rad); return;
-    case 10: geo<10>(entries, passes, rad); return;
-    case 11: geo<11>(entries, passes, rad); return;
-    case 12: geo<12>(entries, passes, rad); return;
-    case 13: geo<13>(entries, passes, rad); return;
-    case 14: geo<14>(entries, passes, rad); return;
+    case 3: geo<3, PLAN>(entries, passes, rad); return;
+    case 4: geo<4, PLAN>(entries, passes, rad); return;
+    case 5: geo<5, PLAN>(entries, passes, rad); return;
+    case 6: geo<6, PLAN>(entries, passes, rad); return;
+    case 7: geo<7, PLAN>(entries, passes, rad); return;
+    case 8: geo<8, PLAN>(entries, passes, rad); return;
+    case 9: geo<9, PLAN>(entries, passes, rad); return;
+    case 10: geo<10, PLAN>(entries, passes, rad); return;
+    case 11: geo<11, PLAN>(entries, passes, rad); return;
+    case 12: geo<12, PLAN>(entries, passes, rad); return;
+    case 13: geo<13, PLAN>(entries, passes, rad); return;
+    case 14: geo<14, PLAN>(entries, passes, rad); return;
   }
   entries = passes = 0;
 }
 
-int twiddle_entries(int log2n) {
+static void geometry(int log2n, int plan, int &entries, int &passes, int *rad) {
+  if (plan == 1) geometry_plan<1>(log2n, entries, passes, rad);
+  else geometry_plan<0>(log2n, entries, passes, rad);
+}
+
+int twiddle_entries(int log2n, int plan) {
   int e, p, r[4];
-  geometry(log2n, e, p, r);
+  geometry(log2n, plan, e, p, r);
   return e;
 }
-int pass_count(int log2n) {
+int pass_count(int log2n, int plan) {
   int e, p, r[4];
-  geometry(log2n, e, p, r);
+  geometry(log2n, plan, e, p, r);
   return p;
 }
+bool second_plan(int log2n) { return has_second_plan(log2n); }
 
 int threads_per_transform(int log2n) {
   switch (log2n) {
@@ -114,9 +121,9 @@ int threads_per_transform(int log2n) {
   return 0;
 }
 
-int pass_radix(int log2n, int q) {
+int pass_radix(int log2n, int plan, int q) {
   int e, p, r[4];
-  geometry(log2n, e, p, r);
+  geometry(log2n, plan, e, p, r);
   return (q >= 0 && q < 4) ? r[q] : 0;
 }
 

@@ -23,44 +23,76 @@
 
 namespace bfp {
 
-// Radix plan per size: E values per thread, up to 4 passes.  Below 256
-// points a transform takes 1 (N <= 16) to 8 threads and a workgroup holds
-// 256 / T transforms; N = 8 and 16 need no exchange at all.
-template <int LOG2N> struct Shape;
-template <> struct Shape<3>  { static constexpr int E = 8,  P = 1, R0 = 8,  R1 = 1,  R2 = 1, R3 = 1; };
-template <> struct Shape<4>  { static constexpr int E = 16, P = 1, R0 = 16, R1 = 1,  R2 = 1, R3 = 1; };
-template <> struct Shape<5>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 2,  R2 = 1, R3 = 1; };
-template <> struct Shape<6>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 4,  R2 = 1, R3 = 1; };
-template <> struct Shape<7>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 8,  R2 = 1, R3 = 1; };
-template <> struct Shape<8>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 16, R2 = 1, R3 = 1; };
-template <> struct Shape<9>  { static constexpr int E = 8,  P = 3, R0 = 8,  R1 = 8,  R2 = 8, R3 = 1; };
-template <> struct Shape<10> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 4, R3 = 1; };
-template <> struct Shape<11> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 8, R3 = 1; };
-template <> struct Shape<12> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 16, R3 = 1; };
-template <> struct Shape<13> { static constexpr int E = 16, P = 4, R0 = 16, R1 = 16, R2 = 16, R3 = 2; };
-template <> struct Shape<14> { static constexpr int E = 16, P = 4, R0 = 16, R1 = 16, R2 = 16, R3 = 4; };
+// Radix plans per size: E values per thread, up to 4 passes.  Plan 0 (the
+// default) takes radix-16 passes where it can; below 256 points a transform
+// takes 1 (N <= 16) to 8 threads and a workgroup holds 256 / T transforms,
+// and N = 8 and 16 need no exchange at all.  Plan 1 is the second candidate
+// the autotuner times: radix-8 passes with 8 values per thread (half the
+// registers, one pass more) from 32 to 4096 points, and at 512, 8192 and
+// 16384 points another radix-16 order (16 16 2; 16 16 8 4; 4 16 16 16).
+// N <= 16 has one plan (a single in-register DFT): plan 1 equals plan 0.
+template <int LOG2N, int PLAN = 0> struct Shape;
+template <> struct Shape<3, 0>  { static constexpr int E = 8,  P = 1, R0 = 8,  R1 = 1,  R2 = 1, R3 = 1; };
+template <> struct Shape<4, 0>  { static constexpr int E = 16, P = 1, R0 = 16, R1 = 1,  R2 = 1, R3 = 1; };
+template <> struct Shape<5, 0>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 2,  R2 = 1, R3 = 1; };
+template <> struct Shape<6, 0>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 4,  R2 = 1, R3 = 1; };
+template <> struct Shape<7, 0>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 8,  R2 = 1, R3 = 1; };
+template <> struct Shape<8, 0>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 16, R2 = 1, R3 = 1; };
+template <> struct Shape<9, 0>  { static constexpr int E = 8,  P = 3, R0 = 8,  R1 = 8,  R2 = 8, R3 = 1; };
+template <> struct Shape<10, 0> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 4, R3 = 1; };
+template <> struct Shape<11, 0> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 8, R3 = 1; };
+template <> struct Shape<12, 0> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 16, R3 = 1; };
+template <> struct Shape<13, 0> { static constexpr int E = 16, P = 4, R0 = 16, R1 = 16, R2 = 16, R3 = 2; };
+template <> struct Shape<14, 0> { static constexpr int E = 16, P = 4, R0 = 16, R1 = 16, R2 = 16, R3 = 4; };
+template <> struct Shape<3, 1> : Shape<3, 0> {};
+template <> struct Shape<4, 1> : Shape<4, 0> {};
+template <> struct Shape<5, 1>  { static constexpr int E = 8,  P = 2, R0 = 8,  R1 = 4,  R2 = 1, R3 = 1; };
+template <> struct Shape<6, 1>  { static constexpr int E = 8,  P = 2, R0 = 8,  R1 = 8,  R2 = 1, R3 = 1; };
+template <> struct Shape<7, 1>  { static constexpr int E = 8,  P = 3, R0 = 8,  R1 = 8,  R2 = 2, R3 = 1; };
+template <> struct Shape<8, 1>  { static constexpr int E = 8,  P = 3, R0 = 8,  R1 = 8,  R2 = 4, R3 = 1; };
+template <> struct Shape<9, 1>  { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 2, R3 = 1; };
+template <> struct Shape<10, 1> { static constexpr int E = 8,  P = 4, R0 = 8,  R1 = 8,  R2 = 8, R3 = 2; };
+template <> struct Shape<11, 1> { static constexpr int E = 8,  P = 4, R0 = 8,  R1 = 8,  R2 = 8, R3 = 4; };
+template <> struct Shape<12, 1> { static constexpr int E = 8,  P = 4, R0 = 8,  R1 = 8,  R2 = 8, R3 = 8; };
+template <> struct Shape<13, 1> { static constexpr int E = 16, P = 4, R0 = 16, R1 = 16, R2 = 8, R3 = 4; };
+template <> struct Shape<14, 1> { static constexpr int E = 16, P = 4, R0 = 4,  R1 = 16, R2 = 16, R3 = 16; };
+// whether a size has a second plan distinct from the first
+constexpr bool has_second_plan(int log2n) { return log2n >= 5 && log2n <= 14; }
 
 // LDS layout of exchange X (written by pass X, read by pass X + 1): element
 // i sits at slot i + C (i >> S).  Each half-wavefront's 32 lanes then hit 32
 // different banks both in the Stockham scatter of pass X and in the reads at
-// t + T e of pass X + 1 (checked by simulation for every size; the bank
-// conflict counter confirms 32 banks per half-wavefront): after a span-1
-// pass, (C, S) = (1, 5); after a span-16 radix-16 pass, (4, 6) ((8, 6) after
-// span 8 at N = 512); after a span-256 pass the scatter is conflict-free
-// unpadded (C = 0).  N = 256 (four transforms per wavefront) keeps one pad
-// slot per 16.  One pad slot per 16 in every exchange made each read 2-way.
-// Below 256 points (at most 8 threads per transform) the single exchange is
-// unpadded.
-template <int LOG2N, int X>
+// t + T e of pass X + 1 (checked by simulation for every size and plan; the
+// bank conflict counter confirms 32 banks per half-wavefront): plan 0 after a
+// span-1 pass, (C, S) = (1, 5); after a span-16 radix-16 pass, (4, 6) ((8, 6)
+// after span 8 at N = 512); after a span-256 pass the scatter is
+// conflict-free unpadded (C = 0).  N = 256 (four transforms per wavefront)
+// keeps one pad slot per 16.  One pad slot per 16 in every exchange made
+// each read 2-way.  Below 256 points (at most 8 threads per transform) the
+// single exchange is unpadded.  Plan 1: (1, 5) after the first pass, then
+// (4, 5) after a second radix-8 pass or (2, 5) after a second radix-16 or
+// radix-4 one, unpadded after the third; from 32 to 128 points (1, 3),
+// (1, 2) and (2, 3), which leave the 2-way conflicts of 4 to 16 threads per
+// transform.
+template <int LOG2N, int X, int PLAN = 0>
 struct Pad {
-  static constexpr int C = LOG2N < 8 ? 0 : LOG2N == 8 ? 1 : X == 0 ? 1 : X == 1 ? (LOG2N == 9 ? 8 : 4) : 0;
-  static constexpr int S = LOG2N == 8 ? 4 : X == 0 ? 5 : 6;
+  static constexpr int C0 = LOG2N < 8 ? 0 : LOG2N == 8 ? 1 : X == 0 ? 1 : X == 1 ? (LOG2N == 9 ? 8 : 4) : 0;
+  static constexpr int S0 = LOG2N == 8 ? 4 : X == 0 ? 5 : 6;
+  static constexpr int C1 = LOG2N == 5 ? 0
+                          : LOG2N == 6 ? 1
+                          : LOG2N == 7 ? (X == 0 ? 1 : 2)
+                          : X == 0 ? 1
+                          : X == 1 ? ((LOG2N == 9 || LOG2N >= 13) ? 2 : 4)
+                          : 0;
+  static constexpr int S1 = LOG2N == 6 ? 3 : LOG2N == 7 ? (X == 0 ? 2 : 3) : 5;
+  static constexpr int C = (PLAN == 0 || LOG2N <= 4) ? C0 : C1;
+  static constexpr int S = (PLAN == 0 || LOG2N <= 4) ? S0 : S1;
   static __host__ __device__ constexpr int at(int i) { return i + C * (i >> S); }
 };
 
-template <int LOG2N>
+template <int LOG2N, int PLAN = 0>
 struct Geometry {
-  typedef Shape<LOG2N> S;
+  typedef Shape<LOG2N, PLAN> S;
   static constexpr int N = 1 << LOG2N;
   static constexpr int E = S::E;
   static constexpr int T = N / E;                    // threads per transform
@@ -70,8 +102,8 @@ struct Geometry {
   static constexpr int LDS_N = [] {
     int m = N + N / 16;
     for (int x = 0; x + 1 < S::P; ++x) {
-      const int slots = (x == 0 ? Pad<LOG2N, 0>::at(N - 1)
-                         : x == 1 ? Pad<LOG2N, 1>::at(N - 1) : Pad<LOG2N, 2>::at(N - 1)) + 1;
+      const int slots = (x == 0 ? Pad<LOG2N, 0, PLAN>::at(N - 1)
+                         : x == 1 ? Pad<LOG2N, 1, PLAN>::at(N - 1) : Pad<LOG2N, 2, PLAN>::at(N - 1)) + 1;
       m = slots > m ? slots : m;
     }
     return m;
@@ -167,9 +199,9 @@ __device__ __forceinline__ void store_row(void *base, long long row, unsigned ti
   }
 }
 
-template <class M, int LOG2N>
+template <class M, int LOG2N, int PLAN = 0>
 struct Engine {
-  typedef Geometry<LOG2N> G;
+  typedef Geometry<LOG2N, PLAN> G;
   typedef typename M::Comp Comp;
   typedef typename M::Lds Lds;
   typedef typename M::Tw Tw;
@@ -216,7 +248,7 @@ struct Engine {
     constexpr int B = E / R;
     constexpr bool LAST = (PASS == G::S::P - 1);
     if constexpr (PASS > 0) {
-      typedef Pad<LOG2N, PASS - 1> In;
+      typedef Pad<LOG2N, PASS - 1, PLAN> In;
       Lds raw[E];
       const int tp = In::at(t);
 #pragma unroll
@@ -239,7 +271,7 @@ struct Engine {
       for (int r = 0; r < R; ++r) v[b + B * r] = u[r];
     }
     if constexpr (!LAST) {
-      typedef Pad<LOG2N, PASS> Out;
+      typedef Pad<LOG2N, PASS, PLAN> Out;
       static_assert(pad_splits<Out, G::N, R, NS>(), "padded offsets of a butterfly must not straddle a pad");
       __syncthreads();  // all reads of the previous contents are done
 #pragma unroll
@@ -305,7 +337,7 @@ struct Engine {
     constexpr bool LAST = (PASS == G::S::P - 1);
     if constexpr (PASS > 0) {
       const Lds *rd = buf[(x - 1) & 1];
-      typedef Pad<LOG2N, PASS - 1> In;
+      typedef Pad<LOG2N, PASS - 1, PLAN> In;
       Lds raw[E];
       const int tp = In::at(t);
 #pragma unroll
@@ -327,7 +359,7 @@ struct Engine {
       for (int r = 0; r < R; ++r) v[b + B * r] = u[r];
     }
     if constexpr (!LAST) {
-      typedef Pad<LOG2N, PASS> Out;
+      typedef Pad<LOG2N, PASS, PLAN> Out;
       static_assert(pad_splits<Out, G::N, R, NS>(), "padded offsets of a butterfly must not straddle a pad");
       Lds *wr = buf[x & 1];
 #pragma unroll
@@ -359,7 +391,7 @@ struct Engine {
     constexpr bool LAST = (PASS == G::S::P - 1);
     if constexpr (PASS > 0) {
       const Lds *rd = buf[NB == 2 ? ((x - 1) & 1) : 0];
-      typedef Pad<LOG2N, PASS - 1> In;
+      typedef Pad<LOG2N, PASS - 1, PLAN> In;
       const int tp = In::at(t);
 #pragma unroll
       for (int q = 0; q < RR; ++q) {
@@ -388,7 +420,7 @@ struct Engine {
       }
     }
     if constexpr (!LAST) {
-      typedef Pad<LOG2N, PASS> Out;
+      typedef Pad<LOG2N, PASS, PLAN> Out;
       static_assert(pad_splits<Out, G::N, R, NS>(), "padded offsets of a butterfly must not straddle a pad");
       if constexpr (NB == 1) __syncthreads();  // the reads of the previous exchange are done
       Lds *wr = buf[NB == 2 ? (x & 1) : 0];

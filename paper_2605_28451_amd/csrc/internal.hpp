@@ -27,6 +27,7 @@ struct RowArgs {
   int rows;
   const void *tw;        // plan twiddle table (mode's twiddle type; with a matrix-core
                          // engine its operands first, the vector table at kMfmaTableBytes)
+  const void *tw_alt;    // the second radix plan's table, or NULL
   const void *filter;    // n elements or NULL
   const void *phasor;    // n FP32 pairs exp(+-i phi_m) or NULL (compress only): applied
                          // to the input, or to the output with KF_POST_PHASOR
@@ -35,6 +36,8 @@ struct RowArgs {
   int grid_limit;        // > 0: persistent grid of at most this many workgroups
   int engine;            // 0: matrix cores where available, 1: vector ALU only
   int rows_per_thread;   // 1, or 2: the multi-row kernel where it covers the variant
+  int radix_plan;        // 0, or 1: the second radix plan (tw_alt) where the multi-row
+                         // kernel covers the variant
   int *grid_out;         // host: set to the launch's workgroup count, or NULL
   double *ent_partial;   // compression to FP32 with phasor: per-workgroup (S, Q) of the
                          // output's entropy sums (one per workgroup: grid_out), or NULL
@@ -54,9 +57,11 @@ hipError_t launch_rows(int mode, int log2n, int op, bool out32, const RowArgs &a
 
 // Number of twiddle-table entries of a size (all passes), and the
 // (pass span, radix) sequence used to fill it on the host.
-int twiddle_entries(int log2n);
-int pass_count(int log2n);
-int pass_radix(int log2n, int p);
+// (plan: 0 or 1, the radix plans of fft_engine.hpp)
+int twiddle_entries(int log2n, int plan = 0);
+int pass_count(int log2n, int plan = 0);
+int pass_radix(int log2n, int plan, int p);
+bool second_plan(int log2n);
 
 // Uneven persistent batch.
 struct UnevenArgs {

@@ -14,6 +14,7 @@ struct bfp_plan_s {
   unsigned flags = 0;
   int device = 0;
   void *tw = nullptr;                         // rows: this size's table
+  void *tw_alt = nullptr;                     // rows: the second radix plan's table
   unsigned long long *nonfinite = nullptr;    // device counter
   void *phasor = nullptr;                     // n FP32 pairs (rows plans)
   // uneven plans
@@ -29,6 +30,7 @@ struct bfp_plan_s {
   int tune_engine = 1;     // 0: matrix cores where available, 1: vector ALU (default)
   int tune_bpc = 0;        // workgroups per CU of a persistent grid, 0 = default
   int tune_rr = 1;         // rows per thread (1, or 2: the multi-row kernel)
+  int tune_plan = 0;       // radix plan (0, or 1 where the size has a second)
   int cu_count = 0;
   int uneven_max_bpc = 1;
   // autofocus workspace

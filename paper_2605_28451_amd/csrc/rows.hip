@@ -426,10 +426,10 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel(RowArgs a) {
 // Otherwise the twiddles come from the table one pass ahead and a group's
 // rows are loaded at its start.  NB LDS buffers per row (2: one barrier per
 // exchange).  Group g holds rows g TPW RR + q TPW + local, q < RR.
-template <class M, int LOG2N, int OP, int V, bool OUT32, int RR, int NB, bool PIPE>
-__global__ void __launch_bounds__(Geometry<LOG2N>::WG) row_kernel_rr(RowArgs a) {
-  typedef Geometry<LOG2N> G;
-  typedef Engine<M, LOG2N> EN;
+template <class M, int LOG2N, int OP, int V, bool OUT32, int RR, int NB, bool PIPE, int PLAN = 0>
+__global__ void __launch_bounds__((Geometry<LOG2N, PLAN>::WG)) row_kernel_rr(RowArgs a) {
+  typedef Geometry<LOG2N, PLAN> G;
+  typedef Engine<M, LOG2N, PLAN> EN;
   typedef typename M::Comp Comp;
   typedef typename M::Store Store;
   typedef typename M::Filt Filt;
@@ -779,6 +779,47 @@ static bool launch_rr(const RowArgs &a, hipStream_t s, hipError_t &err) {
   }
 }
 
+// The second radix plan (a.radix_plan == 1): the multi-row kernel with
+// a.rows_per_thread rows, for the plain forward transform, the BFP inverse
+// and the compression with a filter, its conjugate or a phasor (storage-type
+// output); returns false where it does not apply (other variants, sizes with
+// one plan, rows whose LDS would not leave two workgroups per CU).
+template <int LOG2N, int OP, int V, bool OUT32>
+static bool launch_plan1(const RowArgs &a, hipStream_t s, hipError_t &err) {
+  if constexpr (!has_second_plan(LOG2N) || OUT32 || (V & ~(V_CONJ | V_PHASOR)) != 0 ||
+                ((V & V_PHASOR) && OP != OP_COMPRESS)) {
+    return false;
+  } else {
+    typedef Geometry<LOG2N, 1> G;
+    constexpr long kRow = (long)G::TPW * G::LDS_N * sizeof(typename MODE::Lds);
+    if (a.radix_plan != 1 || !a.tw_alt) return false;
+    RowArgs b = a;
+    b.tw = a.tw_alt;
+    auto go = [&](auto rr) {
+      constexpr int RR = decltype(rr)::value;
+      constexpr int NB = 2 * RR * kRow <= 80 * 1024 ? 2 : 1;
+      unsigned grid = (unsigned)((a.rows + G::TPW * RR - 1) / (G::TPW * RR));
+      if (a.grid_limit > 0 && grid > (unsigned)a.grid_limit) grid = (unsigned)a.grid_limit;
+      if (a.grid_out) *a.grid_out = (int)grid;
+      hipLaunchKernelGGL((row_kernel_rr<MODE, LOG2N, OP, V, OUT32, RR, NB, false, 1>), dim3(grid),
+                         dim3(G::WG), 0, s, b);
+      err = hipGetLastError();
+    };
+    if constexpr (2 * kRow <= 80 * 1024) {
+      if (a.rows_per_thread == 2) {
+        go(std::integral_constant<int, 2>{});
+        return true;
+      }
+    }
+    if constexpr (kRow > 80 * 1024) {
+      return false;
+    } else {
+      go(std::integral_constant<int, 1>{});
+      return true;
+    }
+  }
+}
+
 // a.tw is the plan's table.  Where a matrix-core engine exists, that table
 // starts with the matrix-core operands and the vector engine's twiddles
 // follow at kMfmaTableBytes: variants without a matrix-core kernel run on
@@ -786,6 +827,10 @@ static bool launch_rr(const RowArgs &a, hipStream_t s, hipError_t &err) {
 template <int LOG2N, int OP, int V, bool OUT32>
 static hipError_t launch_one(const RowArgs &a, hipStream_t s) {
   if (a.rows <= 0) return hipSuccess;
+  {
+    hipError_t err = hipSuccess;
+    if (launch_plan1<LOG2N, OP, V, OUT32>(a, s, err)) return err;
+  }
 #if BFP_MODE_ID == 3
   if constexpr (LOG2N == 12) {
     if constexpr ((V & (V_TRANS | V_ADAPT | V_RAMP | V_POST)) == 0) {

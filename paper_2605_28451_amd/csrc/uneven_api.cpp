@@ -33,8 +33,8 @@ int upload(const std::vector<T> &v, T **out) {
 
 int table_for(int log2n, int prec, void **out) {
   int rad[4];
-  const int passes = bfp::pass_count(log2n);
-  for (int p = 0; p < 4; ++p) rad[p] = bfp::pass_radix(log2n, p);
+  const int passes = bfp::pass_count(log2n, 0);
+  for (int p = 0; p < 4; ++p) rad[p] = bfp::pass_radix(log2n, 0, p);
   std::vector<std::complex<double>> t = bfp::twiddle_table(log2n, rad, passes);
   const int fmt = (prec == BFP_FP16 || prec == BFP_FP16_MUL_FP32_ACC) ? BFP_FMT_F16 : BFP_FMT_F32;
   const size_t bytes = std::max<size_t>(16, t.size() * bfp_format_bytes(fmt));

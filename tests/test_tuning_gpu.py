@@ -86,17 +86,74 @@ def test_rows_per_thread_bitwise_equal(mode, n, rows):
     ref = {k: f().clone() for k, f in ops.items()}
     for bpc in (0, 1, 3):
         plan.set_tuning_ex(1, bpc, 2)
-        assert plan.get_tuning_ex() == (1, bpc, 2)
+        assert plan.get_tuning_ex() == (1, bpc, 2, 0)
         for k, f in ops.items():
             same = torch.equal(f(), ref[k])
             assert same, f"{k} blocks_per_cu={bpc}: two rows per thread differ from one"
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp16", "fp16_fp32", "fp16_mul_fp32_acc", "e4m3", "e5m2"])
+@pytest.mark.parametrize("n", [32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384])
+def test_second_radix_plan_matches_oracle(mode, n):
+    # the autotuner's second radix plan (radix-8 passes with 8 values per
+    # thread, or another radix-16 order): every covered variant against the
+    # oracle with the same bars as the first plan, one and two rows per
+    # thread, several transforms per workgroup and a ragged batch; the
+    # variants it does not cover (here the naive schedule) run the first plan
+    need_gpu()
+    from tests.test_paths_gpu import PATH_SQNR_MIN, SMALL_FWD_MIN
+    from tests.gpu_util import FWD_SQNR_MIN
+    rows = 37 if n <= 1024 else 5
+    announce(f"second radix plan mode={mode} n={n}")
+    fmt = api.storage_format(mode)
+    sc = 0.125 if mode in ("e4m3", "e5m2") else 1.0
+    x = scenes.quantize(sc * scenes.gaussian_rows(90 + n, rows, n), fmt)
+    z = scenes.quantize(sc * np.sqrt(n) * scenes.gaussian_rows(91 + n, rows, n), fmt)
+    h = scenes.range_replica_padded(n, max(n // 4, 1))
+    Hq = scenes.quantize(oracle.matched_filter(h, n), api.filter_format(mode))
+    H = api.filter_tensor(h, n, mode)
+    phi = np.random.default_rng(n).uniform(-3, 3, n).astype(np.float32)
+    ph = torch.tensor(phi, device="cuda")
+    plan = api.FFTPlan(n, rows, mode)
+    xd, zd = upload(x, fmt), upload(z, fmt)
+    bar_f = SMALL_FWD_MIN[mode] if n <= 128 else FWD_SQNR_MIN[mode] - (1.5 if n > 4096 else 0.0)
+    for rr in (1, 2):
+        plan.set_tuning_ex(1, 0, rr, 1)
+        assert plan.get_tuning_ex() == (1, 0, rr, 1)
+        got = {
+            "forward": (sqnr_db(oracle.fft(x), download(plan.forward(xd), fmt)), bar_f),
+            "inverse": (sqnr_db(oracle.fft(z, inverse=True), download(plan.inverse_bfp(zd), fmt)), bar_f),
+            "inverse_conj": (sqnr_db(oracle.fft(z * np.conj(Hq), inverse=True),
+                                     download(plan.inverse_bfp(zd, H, conj_filter=True), fmt)), PATH_SQNR_MIN[mode]),
+            "compress": (sqnr_db(oracle.compress(x, Hq), download(plan.range_compress(xd, H), fmt)),
+                         PATH_SQNR_MIN[mode]),
+            "compress_phase": (sqnr_db(oracle.compress(oracle.apply_phase(x, phi.astype(np.float64)), Hq),
+                                       download(plan.azimuth_compress(xd, H, phase=ph), fmt)), PATH_SQNR_MIN[mode]),
+        }
+        for k, (s, bar) in got.items():
+            print(f"[measure] plan1.{mode}.n{n}.rr{rr}.{k} {s:.3f}")
+            assert s >= bar, (k, rr, s, bar)
+    # one and two rows per thread give the same bits within the plan
+    plan.set_tuning_ex(1, 0, 1, 1)
+    a = plan.range_compress(xd, H).clone()
+    plan.set_tuning_ex(1, 3, 2, 1)
+    assert torch.equal(plan.range_compress(xd, H), a)
+
+
+def test_second_plan_rejected_where_absent():
+    need_gpu()
+    for n in (8, 16):
+        with pytest.raises(api._lib.BfpError):
+            api.FFTPlan(n, 4, "fp16").set_tuning_ex(1, 0, 1, 1)
+    with pytest.raises(api._lib.BfpError):
+        api.UnevenPlan([10], [0], "fp16").set_tuning_ex(0, 0, 1, 1)
 
 
 def test_default_rows_per_thread():
     need_gpu()
     for mode, rr in (("fp32", 2), ("fp16", 1), ("fp16_fp32", 2), ("fp16_mul_fp32_acc", 1),
                      ("e4m3", 2), ("e5m2", 2)):
-        assert api.FFTPlan(1024, 4, mode).get_tuning_ex() == (1, -1, rr)
+        assert api.FFTPlan(1024, 4, mode).get_tuning_ex() == (1, -1, rr, 0)
     with pytest.raises(api._lib.BfpError):
         api.FFTPlan(1024, 4, "fp16").set_tuning_ex(1, 0, 3)
 
@@ -121,14 +178,36 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     plan = api.FFTPlan(4096, 512, "fp16_mul_fp32_acc")
     e = autotune.tune(plan, "forward", x, out, reps=5)
     assert e["ms"] > 0 and e["engine"] in (0, 1) and e["blocks_per_cu"] in (-1, 0, 1, 2, 3, 4, 5, 6, 8)
-    assert e["rows_per_thread"] in (1, 2)
+    assert e["rows_per_thread"] in (1, 2) and e["radix_plan"] in (0, 1)
     plan2 = api.FFTPlan(4096, 512, "fp16_mul_fp32_acc")
     assert autotune.apply_cached(plan2, "forward")
-    assert plan2.get_tuning_ex() == (e["engine"], e["blocks_per_cu"], e["rows_per_thread"])
+    assert plan2.get_tuning_ex() == (e["engine"], e["blocks_per_cu"], e["rows_per_thread"], e["radix_plan"])
     # tuned plan still correct
     X = download(plan2.forward(x), "fp16")
     xq = scenes.decode(x.cpu().numpy(), "fp16")
     assert sqnr_db(oracle.fft(xq), X) >= 60.0
+
+
+def test_autotune_over_rotating_sets():
+    # the candidates timed over several buffer pairs; the pick is a valid
+    # tuning and the tuned compression still meets the parity bar
+    need_gpu()
+    from tests.test_paths_gpu import PATH_SQNR_MIN
+    n, rows = 4096, 64
+    sc = scenes.range_scene(seed=2, n_pulses=rows, n=n)
+    echo = scenes.quantize(sc.echo, "fp16")
+    ins = [upload(echo, "fp16") for _ in range(3)]
+    outs = [torch.empty_like(ins[0]) for _ in range(3)]
+    plan = api.FFTPlan(n, rows, "fp16_fp32")
+    H = api.filter_tensor(sc.replica, n, "fp16_fp32")
+    ms = plan.autotune_on(2, ins, outs, H, reps=3)
+    e, b, rr, pl = plan.get_tuning_ex()
+    assert ms > 0 and e == 1 and b in (-1, 0, 1, 2, 3, 4, 5, 6, 8) and rr in (1, 2) and pl in (0, 1)
+    got = download(plan.range_compress(ins[1], H), "fp16")
+    Hq = scenes.quantize(oracle.matched_filter(sc.replica, n), "fp16")
+    assert sqnr_db(oracle.compress(echo, Hq), got) >= PATH_SQNR_MIN["fp16_fp32"]
+    with pytest.raises(ValueError):
+        plan.autotune_on(2, ins, outs[:2], H)
 
 
 def test_uneven_grid_size_does_not_change_results():
