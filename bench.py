@@ -189,14 +189,26 @@ def rotating_sets(make, n_sets):
 def tuning_record(plan, ms):
     e, b, rr, pl = plan.get_tuning_ex()
     return {"engine": "matrix cores" if e == 0 else "vector ALU", "blocks_per_cu": b,
-            "rows_per_thread": rr, "radix_plan": pl, "tuned_ms": round(ms, 5)}
+            "rows_per_thread": rr, "radix_plan": pl,
+            "tuned_ms": None if ms is None else round(ms, 5)}
 
 
-def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30, adaptive=False, tune=True):
+def parse_tuning(text):
+    """'engine,blocks_per_cu,rows_per_thread,radix_plan' -> 4-tuple of ints."""
+    t = tuple(int(v) for v in text.split(","))
+    if len(t) != 4:
+        raise SystemExit("--tuning takes engine,blocks_per_cu,rows_per_thread,radix_plan")
+    return t
+
+
+def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30, adaptive=False, tune=True,
+                   fixed=None):
     """Fused range compression in `mode`, rotating buffers totalling >= min_bytes
     (adaptive: the per-row adaptive block shift, with its exponent rows).
     tune: the library's autotuner picks engine, grid, rows per thread and
-    radix plan on the same rotating buffers before the timed steps."""
+    radix plan on the same rotating buffers before the timed steps; fixed
+    (a tuning 4-tuple) sets them instead, so that a profiled run holds the
+    one kernel configuration only."""
     import torch
     from paper_2605_28451_amd import api, scenes
     sc = scenes.range_scene(seed=2, n_pulses=rows, n=n)
@@ -210,7 +222,13 @@ def bench_compress(mode, rows, n, steps, warmup, min_bytes=1 << 30, adaptive=Fal
     H = api.filter_tensor(sc.replica, n, mode)
 
     exps = [torch.empty(rows, dtype=torch.int32, device="cuda") for _ in range(n_sets)]
-    tuning = tuning_record(plan, plan.autotune_on(2, ins, outs, H, reps=10)) if tune and not adaptive else None
+    if fixed is not None:
+        plan.set_tuning_ex(*fixed)
+        tuning = tuning_record(plan, None)
+    elif tune and not adaptive:
+        tuning = tuning_record(plan, plan.autotune_on(2, ins, outs, H, reps=10))
+    else:
+        tuning = None
 
     def launch(i):
         if adaptive:
@@ -801,6 +819,10 @@ def main():
                     help="profiling mode: run only one secondary workload (the 4096x4096 FP16 SAR "
                          "frame graph, the 20,000-transform uneven batch, or the 4096x4096 "
                          "autofocus loop) for --steps steps; prints its figures, no JSON line")
+    ap.add_argument("--tuning", default=None, metavar="E,B,R,P",
+                    help="with --quick or --kernel-only: set the compression plan's tuning (engine "
+                         "0 = matrix cores / 1 = vector, blocks per CU, rows per thread, radix plan) "
+                         "instead of autotuning, so a profiled run holds one kernel configuration")
     ap.add_argument("--traffic-summary", nargs="+", metavar="MODE:FETCH_DIR:WRITE_DIR", default=None,
                     help="write the HBM traffic record from rocprofv3 --pmc runs of --kernel-only "
                          "(no GPU needed) and print its table")
@@ -825,8 +847,11 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     n, rows = 4096, 2048
+    fixed = parse_tuning(args.tuning) if args.tuning else None
+    if fixed is not None and not (args.quick or args.kernel_only):
+        raise SystemExit("--tuning applies to --quick and --kernel-only runs only")
     if args.kernel_only:
-        r = bench_compress(args.kernel_only, rows, n, args.steps, args.warmup)
+        r = bench_compress(args.kernel_only, rows, n, args.steps, args.warmup, fixed=fixed)
         print(f"[kernel-only] {args.kernel_only} compress: {r['ms_per_launch']:.4f} ms/launch "
               f"{r['hbm_gbs']:.0f} GB/s algorithmic ({r['bytes_per_launch']} B/launch)",
               file=sys.stderr, flush=True)
@@ -851,7 +876,7 @@ def main():
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
 
     log("headline: fused FP16-BFP range compression 2048x4096")
-    head = bench_compress(HEAD_MODE, rows, n, args.steps, args.warmup)
+    head = bench_compress(HEAD_MODE, rows, n, args.steps, args.warmup, fixed=fixed)
     log(f"  {head['gflops']:.0f} GFLOP/s, {head['hbm_gbs']:.0f} GB/s")
     out = {
         "metric": METRIC,
