@@ -42,12 +42,17 @@ def head_kernel_text(t):
             f"a persistent grid of {t['blocks_per_cu']} workgroups per CU")
     return (f"{name}<ModeFP16, 12, OP_COMPRESS, V_PLAIN> (rows.hip), {t['engine']}, radix plan "
             f"{t['radix_plan']} ({RADIX_PLANS_4096[t['radix_plan']]}), {t['rows_per_thread']} row(s) per "
-            f"thread, {grid}; chosen by the library autotuner on the rotating buffers")
+            f"thread, {grid}; " + ("chosen by the library autotuner on the rotating buffers"
+                                   if t["tuned_ms"] is not None else "set by --tuning"))
+
+
 MODE_TEXT = {
     "fp16": "pure FP16 (packed half2 arithmetic, FP16 LDS and twiddles)",
     "fp16_mul_fp32_acc": "FP16 multiply / FP32 accumulate (radix-16 butterflies on the matrix cores)",
 }
 HBM_PEAK_GBS = 8000.0
+# bytes of one stored complex value per precision mode
+STORE_BYTES = {"fp32": 8, "fp16": 4, "fp16_fp32": 4, "fp16_mul_fp32_acc": 4, "e4m3": 2, "e5m2": 2}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "range_compress_2048x4096_traffic.json")
@@ -85,7 +90,8 @@ def traffic_summary(specs):
     into the committed traffic record.  specs: [(mode, fetch_dir, write_dir)],
     each dir holding one run with FETCH_SIZE resp. WRITE_SIZE.  Per counter
     the kernel's mean KiB per dispatch is scaled by known bytes / KiB of the
-    device copy that the same run performs (32 MiB read + 32 MiB written)."""
+    device copy that the same run performs (the compression's bytes: half
+    read, half written; 32 MiB each way in the 4-byte storage modes)."""
     import glob
     import sqlite3
 
@@ -105,21 +111,22 @@ def traffic_summary(specs):
         k = max(kern, key=lambda n: len(agg[n]))
         return k, sum(agg[k]) / len(agg[k]), sum(agg[copy[0]]) / len(agg[copy[0]])
 
-    copy_kib = 32 * 1024  # the copy moves 32 MiB each way
-    rec = {"workload": "fused range compression, 2048 x 4096, FP16 storage",
+    rec = {"workload": "fused range compression, 2048 x 4096 (FP16, FP32 or FP8 storage)",
            "source": "profiles/range_compress_2048x4096_hbm_traffic.md",
            "kernel_sources": KERNEL_SOURCES, "kernel_source_sha256": kernel_source_sha256(),
            "modes": {}}
     lines = ["| mode | kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | copy FETCH / WRITE KiB |",
              "|---|---|---|---|---|"]
-    algo = 2 * 2048 * 4096 * 4
     notes = []
     for mode, fdir, wdir in specs:
+        algo = 2 * 2048 * 4096 * STORE_BYTES[mode]
+        copy_kib = algo // 2 // 1024  # the copy moves the compression's bytes, half each way
         kf, f_kib, cf = means(fdir)
         kw, w_kib, cw = means(wdir)
         ff, fw = copy_kib / cf, copy_kib / cw
         traffic = int(round(f_kib * ff * 1024 + w_kib * fw * 1024))
-        rec["modes"][mode] = {"traffic_bytes": traffic, "fetch_factor": round(ff, 4),
+        rec["modes"][mode] = {"traffic_bytes": traffic, "algorithmic_bytes": algo,
+                              "fetch_factor": round(ff, 4),
                               "write_factor": round(fw, 4), "kernel": kf}
         lines.append(f"| {mode} | `{kf[:70]}` | {f_kib:.1f} | {w_kib:.1f} | {cf:.1f} / {cw:.1f} |")
         notes.append(f"- {mode}: fetch {f_kib:.0f} KiB x {ff:.3f} + write {w_kib:.0f} KiB x {fw:.3f} = "
@@ -130,16 +137,27 @@ def traffic_summary(specs):
     print("\n".join(lines + [""] + notes))
 
 
-def trace_summary(d, top=12):
-    """Markdown table of a rocprofv3 --kernel-trace --stats run (its database)."""
+def trace_summary(d, top=12, tail=None):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (its database).
+    tail: only the last `tail` dispatches of the library's own kernels (the
+    timed region of a run that also autotunes and stages inputs)."""
     import glob
     import sqlite3
     dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
     if len(dbs) != 1:
         raise SystemExit(f"expected one rocprofv3 database under {d}, found {len(dbs)}")
     con = sqlite3.connect(dbs[0])
-    rows = con.execute("select name, count(*), sum(duration), avg(duration), min(duration), "
-                       "max(duration) from kernels group by name order by sum(duration) desc").fetchall()
+    if tail:
+        disp = [r for r in con.execute("select name, duration from kernels order by start").fetchall()
+                if "bfp::" in r[0] or r[0].startswith("_ZN3bfp")][-tail:]
+        agg = {}
+        for name, dur in disp:
+            agg.setdefault(name, []).append(dur)
+        rows = sorted(((k, len(v), sum(v), sum(v) / len(v), min(v), max(v)) for k, v in agg.items()),
+                      key=lambda r: -r[2])
+    else:
+        rows = con.execute("select name, count(*), sum(duration), avg(duration), min(duration), "
+                           "max(duration) from kernels group by name order by sum(duration) desc").fetchall()
     total = sum(r[2] for r in rows) or 1
     out = ["| kernel | calls | average us | min us | max us | share of GPU time |",
            "|---|---|---|---|---|---|"]
@@ -826,11 +844,13 @@ def main():
     ap.add_argument("--traffic-summary", nargs="+", metavar="MODE:FETCH_DIR:WRITE_DIR", default=None,
                     help="write the HBM traffic record from rocprofv3 --pmc runs of --kernel-only "
                          "(no GPU needed) and print its table")
+    ap.add_argument("--trace-tail", type=int, default=None, metavar="K",
+                    help="with --trace-summary: only the last K dispatches of the library's kernels")
     ap.add_argument("--trace-summary", metavar="DIR", default=None,
                     help="print the kernel table of a rocprofv3 --kernel-trace --stats run (no GPU needed)")
     args = ap.parse_args()
     if args.trace_summary:
-        trace_summary(args.trace_summary)
+        trace_summary(args.trace_summary, tail=args.trace_tail)
         return
     if args.traffic_summary:
         traffic_summary([tuple(a.split(":")) for a in args.traffic_summary])
