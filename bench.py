@@ -338,8 +338,9 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
     """Full 4096x4096 range-Doppler frame: fused range compression, LDS-tiled
     corner turn, fused azimuth compression (fused_ct: the corner turn folded
     into the range compression's store, no separate pass).  n_frames
-    independent frame buffer sets rotate (4 x 256 MiB for FP16) and the K
-    frames of a replay are captured once in a HIP graph.  streams > 1: the
+    independent frame buffer sets rotate (4 x 256 MiB for FP16) and two
+    rounds over them (8 frames: a replay carries a fixed cost on the device)
+    are captured once in a HIP graph.  streams > 1: the
     frames of a replay are dealt round-robin to that many streams (default
     priority) forked and joined inside the graph, so independent frames run
     concurrently (frame k's memory-bound corner turn beside frame k+1's
@@ -380,7 +381,8 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
         for i in range(n_frames):
             frame(i)
         torch.cuda.synchronize()
-    reps = max(1, steps // n_frames)
+    per_graph = 2 * n_frames
+    reps = max(1, -(-steps // per_graph))
     if graph:
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -389,15 +391,15 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
         with torch.cuda.stream(s):
             with torch.cuda.graph(g, stream=s):
                 if streams == 1:
-                    for i in range(n_frames):
-                        frame(i)
+                    for i in range(per_graph):
+                        frame(i % n_frames)
                 else:
                     lanes = [s] + side
                     for q in side:
                         q.wait_stream(s)  # fork
-                    for i in range(n_frames):
+                    for i in range(per_graph):
                         with torch.cuda.stream(lanes[i % streams]):
-                            frame(i)
+                            frame(i % n_frames)
                     for q in side:
                         s.wait_stream(q)  # join
         torch.cuda.current_stream().wait_stream(s)
@@ -409,7 +411,7 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
             g.replay()
         e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / (reps * n_frames)
+        ms = e0.elapsed_time(e1) / (reps * per_graph)
     else:
         ms, total = time_launches(frame, n_frames, reps * n_frames, 0)
     # RC r/w, (CT r/w,) AC r/w
@@ -417,7 +419,8 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
     res = {"mode": mode, "ms_per_frame": ms, "frames_per_s": 1e3 / ms,
            "hbm_gbs": bytes_frame / (ms * 1e-3) / 1e9, "bytes_per_frame": bytes_frame,
            "gflops": fft_flops(n, 4 * n) / (ms * 1e-3) / 1e9, "graph": graph,
-           "frames_rotating": n_frames, "corner_turn": "fused into the range store" if fused_ct
+           "frames_rotating": n_frames, "frames_per_replay": per_graph if graph else None,
+           "corner_turn": "fused into the range store" if fused_ct
            else "separate LDS-tiled pass", "concurrent_streams": streams, "tuning": tuning}
     torch.cuda.synchronize()
     res["_img"] = api.to_host(imgs[0], fmt)
@@ -429,10 +432,10 @@ def bench_sar_frame(mode, steps, warmup, n_frames=4, graph=True, fused_ct=False,
 
 def bench_uneven(mode, steps, warmup, with_sqnr=True):
     """The 20,000-transform uneven batch (N log-uniform in 256..16384,
-    random directions) in one persistent launch: the plan's grid autotuned
-    on the batch, the launch (queue reset + persistent kernel) captured in a
-    HIP graph and replayed over two rotating buffer sets; eager launches
-    timed beside it; SQNR per size and direction against the FP64 oracle."""
+    random directions) in one launch: the plan's grid autotuned on the
+    batch, 8 launches captured in a HIP graph over two rotating buffer sets;
+    eager launches timed beside it; SQNR per size and direction against the
+    FP64 oracle."""
     import numpy as np
     import torch
     from paper_2605_28451_amd import api, scenes
@@ -446,30 +449,34 @@ def bench_uneven(mode, steps, warmup, with_sqnr=True):
     tuned_ms = plan.autotune_on(0, ins[0], outs[0], reps=10)
     tuning = plan.get_tuning()
     ms_eager, _ = time_launches(lambda i: plan.execute(ins[i], out=outs[i]), sets, steps, warmup)
+    # a replay carries a fixed cost on the device (measured ≈ 8 us beside
+    # one large kernel): 8 launches per replay, alternating the two sets
+    per_graph = 8
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
     with torch.cuda.stream(s):
         with torch.cuda.graph(g, stream=s):
-            for i in range(sets):
-                plan.execute(ins[i], out=outs[i])
+            for i in range(per_graph):
+                plan.execute(ins[i % sets], out=outs[i % sets])
     torch.cuda.current_stream().wait_stream(s)
     for _ in range(2):
         g.replay()
     torch.cuda.synchronize()
-    reps = max(1, steps // sets)
+    reps = max(1, -(-steps // per_graph))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
         g.replay()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / (reps * sets)
+    ms = e0.elapsed_time(e1) / (reps * per_graph)
     sizes = (1 << ub.log2n.astype("int64"))
     flops = float(np.sum(5.0 * sizes * ub.log2n))
     bytes_ = 2 * x0.numel() * x0.element_size()
     res = {"mode": mode, "transforms": 20000, "ms_per_launch": ms, "ms_per_launch_eager": ms_eager,
-           "graph": "queue reset + persistent kernel captured, 2 rotating buffer sets per replay",
+           "graph": "8 launches per replay over 2 rotating buffer sets (queue reset, when the grid "
+                    "claims from the queue, and the kernel)",
            "autotuned_workgroups_per_cu": tuning[1], "autotune_ms": tuned_ms,
            "gflops": flops / (ms * 1e-3) / 1e9, "hbm_gbs": bytes_ / (ms * 1e-3) / 1e9,
            "bytes_per_launch": bytes_}
@@ -496,11 +503,12 @@ def bench_uneven(mode, steps, warmup, with_sqnr=True):
     return res
 
 
-def bench_autofocus(steps, lr_max=2.5, lr_min=0.02, with_oracle=True):
+def bench_autofocus(steps, lr_max=2.5, lr_min=0.02, with_oracle=True, per_replay=5):
     """`steps` Adam steps (cosine learning-rate schedule from lr_max to
     lr_min, read on the device) of entropy autofocus on the 4096x4096 frame
-    with the injected per-pulse phase error: ms per step (graph replay and
-    eager), entropy and azimuth PSLR/ISLR before and after, beside the image
+    with the injected per-pulse phase error: ms per step (graph replays of
+    `per_replay` iterations each, and eager), entropy and azimuth PSLR/ISLR
+    before and after, beside the image
     the FP64 oracle forms with the true correction, and the GPU gradient at
     phase 0 against FP64 central differences of the oracle's entropy."""
     import numpy as np
@@ -521,16 +529,19 @@ def bench_autofocus(steps, lr_max=2.5, lr_min=0.02, with_oracle=True):
     sched = cosine_schedule(steps, lr_max, lr_min)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
+    k = per_replay if steps % per_replay == 0 else 1
+
     def run(graph):
-        """`steps` iterations from phase 0 (library kernels only; one captured
-        iteration replayed per step when graph)."""
+        """`steps` iterations from phase 0 (library kernels only; k captured
+        iterations per replay when graph)."""
         phi = torch.zeros(n, dtype=torch.float32, device="cuda")
-        loop = AutofocusLoop(plan, rct, Ha, phi, graph=graph, lr_schedule=sched)
+        loop = AutofocusLoop(plan, rct, Ha, phi, graph=graph, lr_schedule=sched,
+                             iterations_per_step=k if graph else 1)
         E0 = float(loop.entropy())
         img0 = api.to_host(loop.img, "fp32")
         torch.cuda.synchronize()
         e0.record()
-        for _ in range(steps):
+        for _ in range(steps // loop.k):
             loop.step()
         e1.record()
         torch.cuda.synchronize()
@@ -558,6 +569,7 @@ def bench_autofocus(steps, lr_max=2.5, lr_min=0.02, with_oracle=True):
 
     out = {"ms_per_step": ms, "ms_per_step_eager": ms_eager, "ms_per_gradient": ms_grad,
            "graph_equals_eager": bool(torch.equal(phi_g, phi_e)), "steps": steps,
+           "iterations_per_replay": k,
            "lr_schedule": f"cosine {lr_max} -> {lr_min} over {steps} steps (device-side)",
            "entropy_before": E0, "entropy_after": float(E)}
     out["pslr_azimuth_db_before"], out["islr_azimuth_db_before"] = az(img0)
@@ -730,6 +742,7 @@ def bench_rcmc_frame(mode, steps, warmup, n_frames=4, streams=1):
     for i in range(warmup):
         frame(i % n_frames)
     torch.cuda.synchronize()
+    per_graph = 2 * n_frames  # two rounds over the sets per replay
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
@@ -739,22 +752,22 @@ def bench_rcmc_frame(mode, steps, warmup, n_frames=4, streams=1):
             lanes = [s] + side
             for q in side:
                 q.wait_stream(s)
-            for i in range(n_frames):
+            for i in range(per_graph):
                 with torch.cuda.stream(lanes[i % streams]):
-                    frame(i)
+                    frame(i % n_frames)
             for q in side:
                 s.wait_stream(q)
     torch.cuda.current_stream().wait_stream(s)
     g.replay()
     torch.cuda.synchronize()
-    reps = max(1, steps // n_frames)
+    reps = max(1, -(-steps // per_graph))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
         g.replay()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / (reps * n_frames)
+    ms = e0.elapsed_time(e1) / (reps * per_graph)
     img = api.to_host(bufs[0][1], fmt)
     pts = [metrics.point_target(img, r0, a0, noise_patch=(r0 + 300, a0 + 300)) for (r0, a0) in sc.targets]
     bytes_frame = 12 * echo0.numel() * echo0.element_size()
@@ -1056,7 +1069,7 @@ def main():
         out["autofocus_4096"] = {
             k: (round(v, 4) if isinstance(v, float) else v) for k, v in af.items() if not k.startswith("_")}
         out["autofocus_4096"]["step"] = ("image + entropy, fused phase gradient, Adam (library kernels), "
-                                         "one HIP graph replay per step")
+                                         "several iterations per HIP graph replay (iterations_per_replay)")
         if not args.no_cpu:
             log("cpu oracle on the other workloads (context)")
             out["cpu_baseline"]["other_workloads"] = cpu_oracle_workloads()

@@ -163,8 +163,12 @@ int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *fi
  * else 0), 0 = one workgroup per group of rows, k > 0 = a persistent grid of
  * k workgroups per CU looping over the rows (in pure FP16 at n <= 4096 this
  * grid overlaps the next rows' loads with the current rows' transforms); uneven plans:
- * workgroups per CU of the persistent launch (0 or above the resident
- * maximum = the maximum).  Results do not depend on blocks_per_cu. */
+ * workgroups per CU of the launch, 0 = the resident maximum (the default: a
+ * persistent grid whose workgroups pull tiles from the work queue), k in
+ * [1, 64] = k per CU; above the resident maximum the hardware queues the
+ * extra workgroups, and a grid with one workgroup per tile or more takes
+ * every tile by workgroup index, without the queue.  Results do not depend
+ * on blocks_per_cu. */
 int fft_plan_set_tuning(bfp_plan p, int engine, int blocks_per_cu);
 int fft_plan_get_tuning(bfp_plan p, int *engine, int *blocks_per_cu);
 
@@ -234,9 +238,9 @@ int fft_uneven_offsets(bfp_plan p, long long *offsets);
 /* Total complex elements of the packed buffer. */
 int fft_uneven_total(bfp_plan p, long long *total);
 /* One launch over the packed batch (in, out: device, fft_uneven_total
- * complex elements in the plan's storage format); a one-thread kernel
- * zeroes the plan's work-queue counter first, so calls on one plan must
- * not overlap. */
+ * complex elements in the plan's storage format).  With a grid smaller
+ * than the tile count a one-thread kernel zeroes the plan's work-queue
+ * counter first, so calls on one plan must not overlap. */
 int fft_exec_uneven(bfp_plan p, const void *in, void *out, void *stream);
 
 /* ------------------------------------------------------------ tables --- */

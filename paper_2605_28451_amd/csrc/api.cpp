@@ -671,7 +671,8 @@ int fft_plan_set_tuning(bfp_plan p, int engine, int blocks_per_cu) {
     return fail(BFP_EINVAL, "blocks_per_cu must be -1 (automatic) or in [0, 64]");
   if (p->kind == 1 && blocks_per_cu < 0) return fail(BFP_EINVAL, "uneven plans take blocks_per_cu >= 0");
   if (p->kind == 1) {
-    const int b = blocks_per_cu == 0 ? p->uneven_max_bpc : std::min(blocks_per_cu, p->uneven_max_bpc);
+    // above the resident maximum the hardware queues the extra workgroups
+    const int b = blocks_per_cu == 0 ? p->uneven_max_bpc : blocks_per_cu;
     p->grid = b * p->cu_count;
   }
   p->tune_engine = engine;
@@ -723,7 +724,12 @@ int fft_autotune_sets(bfp_plan p, int op, const void *const *ins, void *const *o
   if (p->kind == 0 && op == 2 && !filter) return fail(BFP_EINVAL, "compression needs a filter");
   std::vector<bfp_tuning> cands;
   if (p->kind == 1) {
+    // resident grids (the persistent loop over the work queue), then larger
+    // ones, up to one workgroup per tile, whose extra workgroups the
+    // hardware dispatches as resident ones finish
     for (int b = 1; b <= p->uneven_max_bpc; ++b) cands.push_back({0, b, 1, 0});
+    for (int b : {4, 8, 16, 32, 64})
+      if (b > p->uneven_max_bpc) cands.push_back({0, b, 1, 0});
   } else {
     // engine x persistent grid x rows per thread x radix plan (the
     // matrix-core kernels take one row per workgroup and plan 0)

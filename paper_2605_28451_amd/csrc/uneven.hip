@@ -9,6 +9,9 @@
 // items from a device counter until the queue is empty, so the load balances
 // across the 256 CUs without a second launch.  Every workgroup leaves the
 // loop when the counter passes the item count, so the grid always drains.
+// A grid of at least one workgroup per item (the hardware queues the
+// workgroups beyond the resident ones, longest items first) takes each item
+// by its workgroup index and makes no claims.
 #include <type_traits>
 
 #include "fft_engine.hpp"
@@ -123,6 +126,7 @@ __global__ void __launch_bounds__(UNEVEN_WG, uneven_waves_per_simd<M>()) uneven_
       case 14: uneven_item<M, 14>(a, d, lds, tid); break;
       default: break;
     }
+    if ((int)gridDim.x >= a.n_items) break;  // one workgroup per item: no queue
     if (threadIdx.x == 0) item_s = (int)(gridDim.x + atomicAdd(a.queue, 1u));
     __syncthreads();  // LDS of this item is free, and item_s is written
     it = item_s;
@@ -134,10 +138,13 @@ __global__ void __launch_bounds__(UNEVEN_WG, uneven_waves_per_simd<M>()) uneven_
 #define BFP_CAT(a, b) BFP_CAT2(a, b)
 
 hipError_t BFP_CAT(launch_uneven_mode, BFP_MODE_ID)(const UnevenArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(uneven_reset_kernel<MODE>, dim3(1), dim3(1), 0, s, a.queue);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   if (a.n_items <= 0) return hipSuccess;
+  // only a grid smaller than the item count claims from the queue
+  if (grid < a.n_items) {
+    hipLaunchKernelGGL(uneven_reset_kernel<MODE>, dim3(1), dim3(1), 0, s, a.queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(uneven_kernel<MODE>, dim3(grid), dim3(UNEVEN_WG), 0, s, a);
   return hipGetLastError();
 }

@@ -172,7 +172,9 @@ int fft_exec_uneven(bfp_plan p, const void *in, void *out, void *stream) {
   a.tw = p->tw_ptrs_d;
   a.flags = (p->flags & BFP_FLAG_CHECK_FINITE) ? bfp::KF_CHECK_FINITE : 0u;
   a.nonfinite = p->nonfinite;
-  hipError_t e = bfp::launch_uneven(p->prec, a, p->grid, (hipStream_t)stream);
+  // no more workgroups than tiles (the extra ones would only exit)
+  const int grid = std::min(p->grid, p->n_items);
+  hipError_t e = bfp::launch_uneven(p->prec, a, grid, (hipStream_t)stream);
   return e == hipSuccess ? BFP_OK : hip_err(e, "uneven launch");
 }
 

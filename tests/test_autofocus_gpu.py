@@ -293,6 +293,26 @@ def test_autofocus_loop_graph_replays_equal_eager():
     assert int(loop_g.opt.count.item()) == 5 and int(loop_e.opt.count.item()) == 5
     # the steps descend the entropy
     assert float(loop_e.entropy()) < E_first
+    # three iterations per replay: the bits of three single iterations, with
+    # the learning-rate schedule read on the device
+    sched = [0.3, 0.2, 0.1, 0.05, 0.02, 0.01]
+    ph_3 = torch.tensor(phi, dtype=torch.float32, device="cuda")
+    ph_1 = ph_3.clone()
+    loop_3 = AutofocusLoop(AutofocusPlan(npul, nr, "fp16_fp32"), rcd, Ha, ph_3, graph=True,
+                           lr_schedule=sched, iterations_per_step=3)
+    loop_1 = AutofocusLoop(AutofocusPlan(npul, nr, "fp16_fp32"), rcd, Ha, ph_1, graph=False,
+                           lr_schedule=sched)
+    for k in range(2):
+        loop_3.step()
+        torch.cuda.synchronize()
+        for _ in range(3):
+            loop_1.step()
+        torch.cuda.synchronize()
+        assert torch.equal(ph_3, ph_1), f"replay {k}"
+        assert torch.equal(loop_3.stats, loop_1.stats), f"replay {k}"
+    assert int(loop_3.opt.count.item()) == 6
+    with pytest.raises(ValueError):
+        AutofocusLoop(plan_e, rcd, Ha, ph_e, graph=False, iterations_per_step=0)
 
 
 def test_autofocus_full_frame_matches_oracle():

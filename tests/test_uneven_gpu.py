@@ -75,6 +75,12 @@ def test_uneven_full_config_equals_per_size_launches():
     torch.cuda.synchronize()
     yh = y.cpu()
     xh = xd.cpu()
+    # every grid gives the same bits: persistent grids below and at the
+    # resident maximum (work-queue claims), a larger queued grid that still
+    # claims, and one workgroup per tile (no claims)
+    for bpc in (1, 8, 64):
+        plan.set_tuning(1, bpc)
+        assert torch.equal(plan.execute(xd).cpu(), yh), bpc
     for e in range(8, 15):
         n = 1 << e
         for inv in (0, 1):
