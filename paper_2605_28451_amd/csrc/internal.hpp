@@ -67,7 +67,7 @@ bool second_plan(int log2n);
 struct UnevenArgs {
   const void *in;
   void *out;
-  const int4 *items;          // (first position in xform[], count, log2n, 0) per item
+  const int4 *items;          // (first position in xform[], count, log2n, inverse) per item
   // one word per transform, grouped by length, longest first:
   // (element offset << 1) | inverse
   const long long *xform;
@@ -77,6 +77,7 @@ struct UnevenArgs {
   const void *const *tw;      // per-size twiddle tables, index log2n - 8
   unsigned flags;
   unsigned long long *nonfinite;
+  int off32;                  // packed batch below 4 GiB: 32-bit byte offsets
 };
 hipError_t launch_uneven(int mode, const UnevenArgs &a, int grid, hipStream_t stream);
 int uneven_blocks_per_cu(int mode);

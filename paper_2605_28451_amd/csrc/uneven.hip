@@ -42,7 +42,13 @@ typedef ModeE5M2 MODE;
 constexpr int UNEVEN_WG = 1024;
 constexpr int UNEVEN_LDS = 16384 + 16384 / 16;  // largest per-item LDS (elements)
 
-template <class M, int LOG2N>
+// One item: d.y transforms of length 2^LOG2N and one direction (INV: the
+// BFP inverse, the fold of Eq. (1) at the load and the final conjugate in
+// the last pass), each thread holding E elements of one transform.  OFF32:
+// the packed batch spans less than 4 GiB, so every access is a uniform base
+// plus a 32-bit byte offset (one 32-bit add per access instead of a 64-bit
+// address per lane).
+template <class M, int LOG2N, bool INV, bool OFF32>
 __device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typename M::Lds *lds_all,
                                             int tid) {
   typedef Geometry<LOG2N> G;
@@ -50,41 +56,49 @@ __device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typenam
   typedef typename M::Comp Comp;
   typedef typename M::Store Store;
   constexpr int E = G::E, T = G::T;
+  constexpr unsigned SZ = sizeof(Store);
   static_assert((UNEVEN_WG / T) * G::LDS_N <= UNEVEN_LDS, "item exceeds LDS");
   const int local = tid / T;
   const int t = tid & (T - 1);
   const bool active = local < d.y;
-  long long off = 0;
-  bool inv = false;
-  if (active) {
-    const long long w = a.xform[d.x + local];
-    off = w >> 1;
-    inv = (w & 1) != 0;
-  }
+  // element offset of this thread's transform (the word's low bit, the
+  // direction, is the item's)
+  const long long off = active ? (a.xform[d.x + local] >> 1) : 0;
+  const unsigned b0 = ((unsigned)off + (unsigned)t) * SZ;
   Comp v[E];
   if (active) {
     const Store *src = static_cast<const Store *>(a.in) + off;
+    const global_ptr<const char> gb = (global_ptr<const char>)a.in;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      Comp z = M::load(src, t + T * e);
-      v[e] = inv ? conj_pow2<LOG2N>(z) : z;  // BFP fold for inverse transforms
+      Comp z;
+      if constexpr (OFF32) z = M::decode(ld_stream_g((global_ptr<const Store>)(gb + (b0 + (unsigned)(T * e) * SZ))));
+      else z = M::load(src, t + T * e);
+      v[e] = INV ? conj_pow2<LOG2N>(z) : z;  // BFP fold for inverse transforms
     }
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = Comp{};
   }
-  EN::run(v, lds_all + local * G::LDS_N, static_cast<const typename M::Tw *>(a.tw[LOG2N - 8]), t);
+  EN::template run<INV>(v, lds_all + local * G::LDS_N, static_cast<const typename M::Tw *>(a.tw[LOG2N - 8]), t);
   if (active) {
     Store *dst = static_cast<Store *>(a.out) + off;
+    const global_ptr<char> gb = (global_ptr<char>)a.out;
     unsigned bad = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      Comp y = inv ? cconj(v[e]) : v[e];
-      M::store(dst, t + T * e, y);
-      if (a.flags & KF_CHECK_FINITE) bad += finite_c(to_c32(M::round_store(y))) ? 0u : 1u;
+      if constexpr (OFF32) st_stream_g((global_ptr<Store>)(gb + (b0 + (unsigned)(T * e) * SZ)), M::encode(v[e]));
+      else M::store(dst, t + T * e, v[e]);
+      if (a.flags & KF_CHECK_FINITE) bad += finite_c(to_c32(M::round_store(v[e]))) ? 0u : 1u;
     }
     if (bad) atomicAdd(a.nonfinite, (unsigned long long)bad);
   }
+}
+
+template <class M, int LOG2N, bool OFF32>
+__device__ __forceinline__ void uneven_dir(const UnevenArgs &a, int4 d, typename M::Lds *lds, int tid) {
+  if (d.w) uneven_item<M, LOG2N, true, OFF32>(a, d, lds, tid);
+  else uneven_item<M, LOG2N, false, OFF32>(a, d, lds, tid);
 }
 
 template <class M>
@@ -101,7 +115,7 @@ constexpr int uneven_waves_per_simd() {
   return std::is_same<M, ModeFP16>::value ? 8 : 1;
 }
 
-template <class M>
+template <class M, bool OFF32>
 __global__ void __launch_bounds__(UNEVEN_WG, uneven_waves_per_simd<M>()) uneven_kernel(UnevenArgs a) {
   __shared__ typename M::Lds lds[UNEVEN_LDS];
   __shared__ int item_s;
@@ -117,13 +131,13 @@ __global__ void __launch_bounds__(UNEVEN_WG, uneven_waves_per_simd<M>()) uneven_
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     switch (d.z) {
-      case 8: uneven_item<M, 8>(a, d, lds, tid); break;
-      case 9: uneven_item<M, 9>(a, d, lds, tid); break;
-      case 10: uneven_item<M, 10>(a, d, lds, tid); break;
-      case 11: uneven_item<M, 11>(a, d, lds, tid); break;
-      case 12: uneven_item<M, 12>(a, d, lds, tid); break;
-      case 13: uneven_item<M, 13>(a, d, lds, tid); break;
-      case 14: uneven_item<M, 14>(a, d, lds, tid); break;
+      case 8: uneven_dir<M, 8, OFF32>(a, d, lds, tid); break;
+      case 9: uneven_dir<M, 9, OFF32>(a, d, lds, tid); break;
+      case 10: uneven_dir<M, 10, OFF32>(a, d, lds, tid); break;
+      case 11: uneven_dir<M, 11, OFF32>(a, d, lds, tid); break;
+      case 12: uneven_dir<M, 12, OFF32>(a, d, lds, tid); break;
+      case 13: uneven_dir<M, 13, OFF32>(a, d, lds, tid); break;
+      case 14: uneven_dir<M, 14, OFF32>(a, d, lds, tid); break;
       default: break;
     }
     if ((int)gridDim.x >= a.n_items) break;  // one workgroup per item: no queue
@@ -145,15 +159,22 @@ hipError_t BFP_CAT(launch_uneven_mode, BFP_MODE_ID)(const UnevenArgs &a, int gri
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(uneven_kernel<MODE>, dim3(grid), dim3(UNEVEN_WG), 0, s, a);
+  if (a.off32)
+    hipLaunchKernelGGL((uneven_kernel<MODE, true>), dim3(grid), dim3(UNEVEN_WG), 0, s, a);
+  else
+    hipLaunchKernelGGL((uneven_kernel<MODE, false>), dim3(grid), dim3(UNEVEN_WG), 0, s, a);
   return hipGetLastError();
 }
 
 int BFP_CAT(uneven_blocks_per_cu_mode, BFP_MODE_ID)() {
-  int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, uneven_kernel<MODE>, UNEVEN_WG, 0) !=
-      hipSuccess)
+  // the resident workgroups of the form with fewer
+  int b32 = 0, b64 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b32, uneven_kernel<MODE, true>, UNEVEN_WG, 0) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b64, uneven_kernel<MODE, false>, UNEVEN_WG, 0) !=
+          hipSuccess)
     return 1;
+  const int blocks = b32 < b64 ? b32 : b64;
   return blocks < 1 ? 1 : blocks;
 }
 

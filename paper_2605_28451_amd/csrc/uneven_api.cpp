@@ -83,18 +83,21 @@ int fft_plan_uneven(bfp_plan *out, int count, const int *log2n, const unsigned c
   }
   p->total = off;
 
-  // group by length, longest first (stable within a length)
+  // group by length, longest first, then by direction (stable within a
+  // group): every item holds transforms of one length and one direction
   std::vector<int> order(count);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return log2n[a] > log2n[b]; });
+  auto dir = [&](int i) { return inverse[i] ? 1 : 0; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return log2n[a] != log2n[b] ? log2n[a] > log2n[b] : dir(a) < dir(b);
+  });
   std::vector<int4> items;
   for (int s = 0; s < count;) {
-    const int l = log2n[order[s]];
+    const int l = log2n[order[s]], w = dir(order[s]);
     int e = s;
-    while (e < count && log2n[order[e]] == l) ++e;
+    while (e < count && log2n[order[e]] == l && dir(order[e]) == w) ++e;
     const int per = bfp::kUnevenWG / bfp::threads_per_transform(l);
-    for (int i = s; i < e; i += per) items.push_back(make_int4(i, std::min(per, e - i), l, 0));
+    for (int i = s; i < e; i += per) items.push_back(make_int4(i, std::min(per, e - i), l, w));
     s = e;
   }
   p->n_items = (int)items.size();
@@ -172,6 +175,7 @@ int fft_exec_uneven(bfp_plan p, const void *in, void *out, void *stream) {
   a.tw = p->tw_ptrs_d;
   a.flags = (p->flags & BFP_FLAG_CHECK_FINITE) ? bfp::KF_CHECK_FINITE : 0u;
   a.nonfinite = p->nonfinite;
+  a.off32 = p->total * (long long)bfp_storage_bytes(p->prec) < (1ll << 32) ? 1 : 0;
   // no more workgroups than tiles (the extra ones would only exit)
   const int grid = std::min(p->grid, p->n_items);
   hipError_t e = bfp::launch_uneven(p->prec, a, grid, (hipStream_t)stream);

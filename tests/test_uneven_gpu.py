@@ -103,6 +103,39 @@ def test_uneven_full_config_equals_per_size_launches():
         assert sqnr_db(ref, yq[ub.offsets[i]:ub.offsets[i] + n]) >= 56.0  # 59.8 at worst
 
 
+def test_uneven_beyond_4gib_uses_64bit_offsets():
+    # a packed batch above 4 GiB (65540 transforms of 16384 in FP16, then
+    # mixed small ones of both directions at offsets past 4 GiB) takes the
+    # kernel's 64-bit addressing; bitwise equal to per-size row launches
+    need_gpu()
+    announce("uneven beyond 4 GiB fp16")
+    big = 65540
+    rng = np.random.default_rng(21)
+    small = rng.integers(8, 14, 300)
+    log2n = np.concatenate([np.full(big, 14), small]).astype(np.int32)
+    inv = np.concatenate([np.zeros(big, np.uint8), rng.integers(0, 2, 300).astype(np.uint8)])
+    plan = api.UnevenPlan(log2n, inv, "fp16")
+    assert plan.total * 4 > (1 << 32)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.randn((plan.total, 2), generator=g, device="cuda").to(torch.float16)
+    y = plan.execute(x)
+    nb = big * 16384
+    ref = api.FFTPlan(16384, big, "fp16").forward(x[:nb].view(big, 16384, 2))
+    assert torch.equal(y[:nb].view(big, 16384, 2), ref)
+    del ref
+    for e in range(8, 14):
+        n = 1 << e
+        for d in (0, 1):
+            idx = [big + i for i in np.nonzero((small == e) & (inv[big:] == d))[0]]
+            if not idx:
+                continue
+            rows = torch.stack([x[plan.offsets[i]:plan.offsets[i] + n] for i in idx]).contiguous()
+            p = api.FFTPlan(n, len(idx), "fp16")
+            r = p.inverse_bfp(rows) if d else p.forward(rows)
+            got = torch.stack([y[plan.offsets[i]:plan.offsets[i] + n] for i in idx])
+            assert torch.equal(got, r), (e, d)
+
+
 def test_uneven_empty_and_single():
     need_gpu()
     p0 = api.UnevenPlan(np.zeros(0, np.int32), np.zeros(0, np.uint8), "fp16")
