@@ -84,14 +84,19 @@ __device__ __forceinline__ void uneven_item(const UnevenArgs &a, int4 d, typenam
   if (active) {
     Store *dst = static_cast<Store *>(a.out) + off;
     const global_ptr<char> gb = (global_ptr<char>)a.out;
-    unsigned bad = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       if constexpr (OFF32) st_stream_g((global_ptr<Store>)(gb + (b0 + (unsigned)(T * e) * SZ)), M::encode(v[e]));
       else M::store(dst, t + T * e, v[e]);
-      if (a.flags & KF_CHECK_FINITE) bad += finite_c(to_c32(M::round_store(v[e]))) ? 0u : 1u;
     }
-    if (bad) atomicAdd(a.nonfinite, (unsigned long long)bad);
+    // the check as a branch of its own (inside the store loop the compiler
+    // evaluates it for every element whatever the flag)
+    if (a.flags & KF_CHECK_FINITE) {
+      unsigned bad = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) bad += finite_c(to_c32(M::round_store(v[e]))) ? 0u : 1u;
+      if (bad) atomicAdd(a.nonfinite, (unsigned long long)bad);
+    }
   }
 }
 
