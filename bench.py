@@ -856,6 +856,10 @@ def main():
                     help="profiling mode: run only one secondary workload (the 4096x4096 FP16 SAR "
                          "frame graph, the 20,000-transform uneven batch, or the 4096x4096 "
                          "autofocus loop) for --steps steps; prints its figures, no JSON line")
+    ap.add_argument("--uneven-size", type=int, default=None, metavar="L",
+                    help="profiling mode: 128 MiB of forward transforms of 2^L points (FP16) through "
+                         "the uneven kernel (one workgroup per item) and then through the row kernel, "
+                         "--steps launches each; prints no JSON")
     ap.add_argument("--tuning", default=None, metavar="E,B,R,P",
                     help="with --quick or --kernel-only: set the compression plan's tuning (engine "
                          "0 = matrix cores / 1 = vector, blocks per CU, rows per thread, radix plan) "
@@ -889,6 +893,24 @@ def main():
     fixed = parse_tuning(args.tuning) if args.tuning else None
     if fixed is not None and not (args.quick or args.kernel_only):
         raise SystemExit("--tuning applies to --quick and --kernel-only runs only")
+    if args.uneven_size is not None:
+        if not 8 <= args.uneven_size <= 14:
+            raise SystemExit("--uneven-size takes 8..14")
+        import numpy as np
+        e = args.uneven_size
+        nn, c = 1 << e, (1 << 25) >> e
+        from paper_2605_28451_amd import scenes
+        x = api.to_device(scenes.gaussian_rows(1, 64, nn), "fp16").repeat(c // 64, 1, 1).contiguous()
+        o = torch.empty_like(x)
+        up = api.UnevenPlan(np.full(c, e, np.int32), np.zeros(c, np.uint8), "fp16")
+        up.set_tuning(1, 64)
+        ms_u, _ = time_launches(lambda i: up.execute(x.view(-1, 2), out=o.view(-1, 2)), 1, args.steps,
+                                args.warmup)
+        rp = api.FFTPlan(nn, c, "fp16")
+        ms_r, _ = time_launches(lambda i: rp.forward(x, out=o), 1, args.steps, args.warmup)
+        print(f"[uneven-size] n={nn} transforms={c}: uneven kernel {ms_u * 1e3:.1f} us, "
+              f"row kernel {ms_r * 1e3:.1f} us", file=sys.stderr, flush=True)
+        return
     if args.kernel_only:
         r = bench_compress(args.kernel_only, rows, n, args.steps, args.warmup, fixed=fixed)
         print(f"[kernel-only] {args.kernel_only} compress: {r['ms_per_launch']:.4f} ms/launch "
