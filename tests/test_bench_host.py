@@ -83,3 +83,47 @@ def test_measured_traffic_only_for_the_sources_it_was_taken_on(tmp_path, monkeyp
     rec["kernel_source_sha256"] = "0" * 64
     out.write_text(json.dumps(rec))
     assert bench.measured_traffic("fp16") is None
+
+
+def test_trace_summary_tail_keeps_the_last_library_dispatches(tmp_path, capsys):
+    # the timed region: the last K dispatches of the library's kernels
+    # (demangled bfp:: names and mangled _ZN3bfp ones), runtime copies left out
+    path = str(tmp_path / "host" / "t_results.db")
+    os.makedirs(os.path.dirname(path))
+    con = sqlite3.connect(path)
+    con.execute("create table kernels (name text, start integer, duration integer)")
+    con.executemany("insert into kernels values (?, ?, ?)", [
+        ("void bfp::row_kernel<x>(bfp::RowArgs)", 1, 90000),       # autotuning, dropped
+        ("__amd_rocclr_copyBuffer", 2, 5000),
+        ("void bfp::row_kernel<x>(bfp::RowArgs)", 3, 30000),
+        ("_ZN3bfp17phase_grad_kernelE", 4, 60000),
+        ("__amd_rocclr_copyBuffer", 5, 7000),
+        ("void bfp::row_kernel<x>(bfp::RowArgs)", 6, 32000)])
+    con.commit()
+    con.close()
+    bench.trace_summary(str(tmp_path), tail=3)
+    out = capsys.readouterr().out.splitlines()
+    assert out[2] == "| `void bfp::row_kernel<x>(bfp::RowArgs)` | 2 | 31.00 | 30.00 | 32.00 | 50.8% |"
+    assert out[3] == "| `_ZN3bfp17phase_grad_kernelE` | 1 | 60.00 | 60.00 | 60.00 | 49.2% |"
+    assert len(out) == 4
+
+
+def test_traffic_summary_uses_each_modes_bytes(tmp_path, monkeypatch, capsys):
+    # FP32 storage: 128 MiB per launch, the calibration copy moves 64 MiB each way
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    _pmc_db(str(tmp_path / "f" / "x" / "pmc_results.db"), [32768.0], 32768.0)
+    _pmc_db(str(tmp_path / "w" / "x" / "pmc_results.db"), [65536.0], 65536.0)
+    bench.traffic_summary([("fp32", str(tmp_path / "f"), str(tmp_path / "w"))])
+    m = json.loads(out.read_text())["modes"]["fp32"]
+    assert m["algorithmic_bytes"] == 134217728
+    assert m["fetch_factor"] == 2.0 and m["write_factor"] == 1.0
+    assert m["traffic_bytes"] == 134217728
+    assert "(1.000 x algorithmic 134217728 B)" in capsys.readouterr().out
+
+
+def test_parse_tuning():
+    assert bench.parse_tuning("1,8,1,0") == (1, 8, 1, 0)
+    assert bench.parse_tuning("0,-1,2,1") == (0, -1, 2, 1)
+    with pytest.raises(SystemExit):
+        bench.parse_tuning("1,8,1")
