@@ -900,7 +900,6 @@ def main():
     if args.uneven_size is not None:
         if not 8 <= args.uneven_size <= 14:
             raise SystemExit("--uneven-size takes 8..14")
-        import numpy as np
         e = args.uneven_size
         nn, c = 1 << e, (1 << 25) >> e
         from paper_2605_28451_amd import scenes
