@@ -1,4 +1,4 @@
-"""Autotuner driver with a JSON cache.
+"""Autotuner front end with a JSON cache.
 
 The timing loop runs in the library (fft_autotune: every candidate of the
 plan's tuning space -- engine, persistent-grid size, rows per thread and
