@@ -1023,6 +1023,8 @@ def main():
         log("plain forward FFT n=4096 batch=64 (latency-bound shape)")
         r = bench_fft("fp16", 64, n, args.steps, args.warmup, min_bytes=0)
         fft["fp16_batch64"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}
+        fft["fp16_batch64"]["note"] = ("the 64 x 4096 round-trip workload's shape: 1 MiB each way, "
+                                       "bound by launch latency, not by HBM")
         out["fft_n4096"] = fft
         # the same ratio on the plain forward FFT (1 GiB each way, both modes)
         out["fp16_over_fp32_plain_fft"] = round(fft["fp16"]["gflops"] / fft["fp32"]["gflops"], 3)
