@@ -36,11 +36,19 @@ def head_kernel_text(t):
     """The headline kernel the autotuner chose (rows.hip)."""
     if t is None:
         return "row_kernel (rows.hip), default tuning"
-    name = "row_kernel_rr" if (t["rows_per_thread"] > 1 or t["radix_plan"] == 1) else "row_kernel"
+    if t["rows_per_thread"] == 1 and t["radix_plan"] == 0 and t["blocks_per_cu"] != 0 \
+            and t["engine"] != "matrix cores":
+        # persistent grids of the pure-FP16 compression at 4096 points: the
+        # pipelined form with one LDS buffer per row
+        kern = "row_kernel_rr<ModeFP16, 12, OP_COMPRESS, V_PLAIN, RR = 1, NB = 1, PIPE>"
+    elif t["rows_per_thread"] > 1 or t["radix_plan"] == 1:
+        kern = "row_kernel_rr<ModeFP16, 12, OP_COMPRESS, V_PLAIN>"
+    else:
+        kern = "row_kernel<ModeFP16, 12, OP_COMPRESS, V_PLAIN>"
     grid = ("one workgroup per row group" if t["blocks_per_cu"] == 0 else
             "the default grid" if t["blocks_per_cu"] < 0 else
             f"a persistent grid of {t['blocks_per_cu']} workgroups per CU")
-    return (f"{name}<ModeFP16, 12, OP_COMPRESS, V_PLAIN> (rows.hip), {t['engine']}, radix plan "
+    return (f"{kern} (rows.hip), {t['engine']}, radix plan "
             f"{t['radix_plan']} ({RADIX_PLANS_4096[t['radix_plan']]}), {t['rows_per_thread']} row(s) per "
             f"thread, {grid}; " + ("chosen by the library autotuner on the rotating buffers"
                                    if t["tuned_ms"] is not None else "set by --tuning"))

@@ -449,15 +449,16 @@ struct Engine {
     }
   }
 
-  // RR rows with register twiddles, two buffers.
-  template <bool CJ, int RR>
+  // RR rows with register twiddles, NB buffers per row (2: one barrier per
+  // exchange; 1: two).
+  template <bool CJ, int RR, int NB = 2>
   static __device__ __forceinline__ void run_regs_rr(Comp (&v)[RR][E], Lds *const (&buf)[2], unsigned &x,
                                                      int t, TwRegs &W) {
     static_assert(kTwRegs, "register twiddles need packed FP16 data and twiddles and at most 3 passes");
     auto none = [] {};
-    pass_rr<0, CJ, RR, 2>(v, buf, x, t, W.w[0], none);
-    if constexpr (G::S::P > 1) pass_rr<1, CJ, RR, 2>(v, buf, x, t, W.w[0], none);
-    if constexpr (G::S::P > 2) pass_rr<2, CJ, RR, 2>(v, buf, x, t, W.w[1], none);
+    pass_rr<0, CJ, RR, NB>(v, buf, x, t, W.w[0], none);
+    if constexpr (G::S::P > 1) pass_rr<1, CJ, RR, NB>(v, buf, x, t, W.w[0], none);
+    if constexpr (G::S::P > 2) pass_rr<2, CJ, RR, NB>(v, buf, x, t, W.w[1], none);
     conj_unfolded_rr<CJ>(v);
   }
 
