@@ -769,10 +769,15 @@ static bool launch_rr(const RowArgs &a, hipStream_t s, hipError_t &err) {
     return false;
   } else {
     constexpr int RR = 2;
-    // LDS per buffer set; two workgroups must fit a CU (160 KiB): two
-    // buffers per row where they do, else one, else no multi-row kernel
+    // LDS per buffer set; two workgroups must fit a CU (160 KiB), else no
+    // multi-row kernel.  One buffer per row (two barriers per exchange)
+    // except for the pipelined pure-FP16 form: with FP32 arithmetic the LDS
+    // saved, twice the workgroups per CU, is worth more than the barrier
+    // (FP16 storage / FP32 arithmetic at 4096 points: 60.0 against 64.7 us
+    // for 4096 x 4096 compressions, and the autofocus image 72-75 against
+    // 80-85 us)
     constexpr long kSet = (long)G::TPW * RR * G::LDS_N * sizeof(typename MODE::Lds);
-    constexpr int NB = 2 * kSet <= 80 * 1024 ? 2 : 1;
+    constexpr int NB = (Engine<MODE, LOG2N>::kTwRegs && 2 * kSet <= 80 * 1024) ? 2 : 1;
     if constexpr (kSet > 80 * 1024) {
       return false;
     } else {
