@@ -192,7 +192,12 @@ int fft_plan_get_tuning(bfp_plan p, int *engine, int *blocks_per_cu);
  * Uneven plans take rows_per_thread = 1 and radix_plan = 0.  A new plan has
  * {1, -1, 2, 0} in the modes with FP32 arithmetic (BFP_FP32,
  * BFP_FP16_STORE_FP32_COMPUTE and the FP8-storage modes) and {1, -1, 1, 0}
- * in BFP_FP16 and BFP_FP16_MUL_FP32_ACC.  Errors: BFP_EINVAL. */
+ * in BFP_FP16 and BFP_FP16_MUL_FP32_ACC; a plan made with
+ * BFP_FLAG_AUTOFOCUS takes radix_plan 1 where its size has two plans (the
+ * phase gradient, sar_azimuth_phase_grad, runs that plan where its
+ * workgroups hold no more transforms than plan 0's, and plan 0 otherwise;
+ * the FP32-output image of sar_azimuth_image_entropy always runs plan 0).
+ * Errors: BFP_EINVAL. */
 typedef struct {
   int engine;
   int blocks_per_cu;

@@ -314,6 +314,9 @@ int fft_plan(bfp_plan *out, int n, int batch, int prec, unsigned flags) {
   p->tune_engine = 1;
   p->tune_bpc = kAutoBpc;
   p->tune_rr = default_rows_per_thread(prec);
+  // autofocus plans: the second radix plan, whose phase gradient runs twice
+  // the wavefronts per row in the same LDS (82 against 98 us at 4096 x 4096)
+  if ((flags & BFP_FLAG_AUTOFOCUS) && bfp::second_plan(l)) p->tune_plan = 1;
   st = upload_twiddles(l, prec, 0, &p->tw);
   if (!st && bfp::second_plan(l)) st = upload_twiddles(l, prec, 1, &p->tw_alt);
   if (st) {
@@ -655,10 +658,12 @@ int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, co
   a.filter = h_az;
   a.phasor = az_plan->phasor;
   a.tw32 = az_plan->tw32;
+  a.tw32_alt = az_plan->tw_alt;  // FP32 as well in both admitted modes
   a.partial = az_plan->pg_partial;
   a.grad = grad_phase;
   a.rows = n_range;
   a.rows_per_thread = az_plan->tune_rr;
+  a.radix_plan = az_plan->tune_plan;
   e = bfp::launch_phase_grad(az_plan->prec == BFP_FP16_STORE_FP32_COMPUTE, az_plan->log2n, a,
                              stats != nullptr, (hipStream_t)stream);
   return e == hipSuccess ? BFP_OK : hip_fail(e, "phase gradient launch");

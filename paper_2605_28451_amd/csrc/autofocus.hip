@@ -226,10 +226,10 @@ hipError_t launch_adam(float *phase, const float *grad, float *m, float *v, unsi
 // the twiddles and the barriers of each LDS exchange); the per-pulse sums of
 // the RR rows go into the same registers, row by row in order.  NB LDS
 // buffers per row (2: one barrier per exchange).
-template <class StoreT, int LOG2N, bool FUSED, int RR, int NB>
-__global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGradArgs a) {
-  typedef Geometry<LOG2N> G;
-  typedef Engine<ModeFP32, LOG2N> EN;
+template <class StoreT, int LOG2N, bool FUSED, int RR, int NB, int PLAN = 0>
+__global__ void __launch_bounds__((Geometry<LOG2N, PLAN>::WG)) phase_grad_kernel(PhaseGradArgs a) {
+  typedef Geometry<LOG2N, PLAN> G;
+  typedef Engine<ModeFP32, LOG2N, PLAN> EN;
   constexpr int E = G::E, T = G::T, N = G::N;
   constexpr int ROWS = G::TPW * RR;
   __shared__ c32 lds_all[NB * ROWS * G::LDS_N];
@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(Geometry<LOG2N>::WG) phase_grad_kernel(PhaseGr
   c32 *lds = lds_all + local * RR * G::LDS_N;
   c32 *const buf[2] = {lds, lds + (NB == 2 ? ROWS * G::LDS_N : 0)};
   unsigned xch = 0;
-  const c32 *tw = static_cast<const c32 *>(a.tw32);
+  const c32 *tw = static_cast<const c32 *>(PLAN == 0 ? a.tw32 : a.tw32_alt);
   const StoreT *flt = static_cast<const StoreT *>(a.filter);
   const c32 *ph = static_cast<const c32 *>(a.phasor);
   const c32 *gin = static_cast<const c32 *>(a.gimg);
@@ -332,15 +332,15 @@ __global__ void __launch_bounds__(256) partial_sum_kernel(const float *__restric
     out[(long long)blockIdx.y * n + m] = (float)(((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c]);
 }
 
-template <class StoreT, int LOG2N, int RR, int NB>
+template <class StoreT, int LOG2N, int RR, int NB, int PLAN = 0>
 static hipError_t launch_pg_rr(const PhaseGradArgs &a, bool fused, hipStream_t s) {
-  typedef Geometry<LOG2N> G;
+  typedef Geometry<LOG2N, PLAN> G;
   const int groups = (a.rows + G::TPW * RR - 1) / (G::TPW * RR);
   const int grid = groups < kPhaseGradBlocks ? (groups < 1 ? 1 : groups) : kPhaseGradBlocks;
   if (fused)
-    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, true, RR, NB>), dim3(grid), dim3(G::WG), 0, s, a);
+    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, true, RR, NB, PLAN>), dim3(grid), dim3(G::WG), 0, s, a);
   else
-    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, false, RR, NB>), dim3(grid), dim3(G::WG), 0, s, a);
+    hipLaunchKernelGGL((phase_grad_kernel<StoreT, LOG2N, false, RR, NB, PLAN>), dim3(grid), dim3(G::WG), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = G::N;
@@ -357,14 +357,23 @@ static hipError_t launch_pg_rr(const PhaseGradArgs &a, bool fused, hipStream_t s
 
 // Two rows per iteration where the plan asks for it and their FP32 exchange
 // buffers leave LDS for two workgroups per CU (n <= 4096); one otherwise.
-template <class StoreT, int LOG2N>
-static hipError_t launch_pg(const PhaseGradArgs &a, bool fused, hipStream_t s) {
-  typedef Geometry<LOG2N> G;
+// The plan's radix plan 1 where that plan's workgroups hold no more
+// transforms than plan 0's (the partials are sized for plan 0).
+template <class StoreT, int LOG2N, int PLAN>
+static hipError_t launch_pg_plan(const PhaseGradArgs &a, bool fused, hipStream_t s) {
+  typedef Geometry<LOG2N, PLAN> G;
   constexpr long kSet2 = (long)G::TPW * 2 * G::LDS_N * sizeof(c32);
   if constexpr (kSet2 <= 80 * 1024) {
-    if (a.rows_per_thread == 2) return launch_pg_rr<StoreT, LOG2N, 2, 1>(a, fused, s);
+    if (a.rows_per_thread == 2) return launch_pg_rr<StoreT, LOG2N, 2, 1, PLAN>(a, fused, s);
   }
-  return launch_pg_rr<StoreT, LOG2N, 1, 1>(a, fused, s);
+  return launch_pg_rr<StoreT, LOG2N, 1, 1, PLAN>(a, fused, s);
+}
+template <class StoreT, int LOG2N>
+static hipError_t launch_pg(const PhaseGradArgs &a, bool fused, hipStream_t s) {
+  if constexpr (has_second_plan(LOG2N) && Geometry<LOG2N, 1>::TPW <= Geometry<LOG2N, 0>::TPW) {
+    if (a.radix_plan == 1 && a.tw32_alt) return launch_pg_plan<StoreT, LOG2N, 1>(a, fused, s);
+  }
+  return launch_pg_plan<StoreT, LOG2N, 0>(a, fused, s);
 }
 
 long long phase_grad_scratch_floats(int log2n) {

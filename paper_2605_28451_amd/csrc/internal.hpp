@@ -109,11 +109,13 @@ struct PhaseGradArgs {
   const void *rc_t;      // range-compressed data, plan storage (FP16 or FP32)
   const void *filter;    // azimuth filter, plan filter format
   const void *phasor;    // FP32 pairs exp(i phi_m)
-  const void *tw32;      // FP32 twiddle table of the size
+  const void *tw32;      // FP32 twiddle table of the size (radix plan 0)
+  const void *tw32_alt;  // FP32 twiddle table of radix plan 1 (sizes with two plans)
   float *partial;        // kPhaseGradBlocks * transforms-per-workgroup rows of n floats
   float *grad;           // n floats out
   int rows;
   int rows_per_thread;   // 1, or 2 where the kernel fits (n <= 4096)
+  int radix_plan;        // 0, or 1 where that plan fits the partials (see launch_pg)
 };
 // (S, Q, E) from `blocks` partial (S, Q) pairs, summed in a fixed order.
 hipError_t launch_entropy_final(const double *partial, int blocks, double *stats, hipStream_t s);

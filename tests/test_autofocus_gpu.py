@@ -29,10 +29,13 @@ def _small_case(seed=5, nr=128, npul=1024):
     return sc, rc_t, phi
 
 
-@pytest.mark.parametrize("mode", ["fp32", "fp16_fp32"])
-def test_phase_gradient_matches_fp64(mode):
+@pytest.mark.parametrize("mode,rr,radix_plan", [("fp32", 2, 0), ("fp16_fp32", 2, 0), ("fp32", 1, 0),
+                                                 ("fp16_fp32", 1, 1), ("fp32", 2, 1), ("fp16_fp32", 2, 1)])
+def test_phase_gradient_matches_fp64(mode, rr, radix_plan):
+    # every kernel form of the gradient: one or two rows per thread, radix
+    # plan 0 (radix-16 passes) or 1 (radix-8, twice the wavefronts per row)
     need_gpu()
-    announce(f"autofocus gradient small mode={mode}")
+    announce(f"autofocus gradient small mode={mode} rr={rr} plan={radix_plan}")
     sc, rc_t, phi = _small_case()
     nr, npul = rc_t.shape
     fmt = api.storage_format(mode)
@@ -42,6 +45,7 @@ def test_phase_gradient_matches_fp64(mode):
     Haq = scenes.quantize(oracle.matched_filter(sc.azimuth_replica, npul), api.filter_format(mode))
     E_ref, g_ref = oracle.autofocus(rcq, Haq, phi32)
     plan = AutofocusPlan(npul, nr, mode)
+    plan.set_tuning_ex(1, -1, rr, radix_plan)
     ph = torch.tensor(phi32, dtype=torch.float32, device="cuda")
     E, g, _ = entropy_and_grad(plan, upload(rcq, fmt), Ha, ph)
     E = float(E.item())

@@ -154,6 +154,10 @@ def test_default_rows_per_thread():
     for mode, rr in (("fp32", 2), ("fp16", 1), ("fp16_fp32", 2), ("fp16_mul_fp32_acc", 1),
                      ("e4m3", 2), ("e5m2", 2)):
         assert api.FFTPlan(1024, 4, mode).get_tuning_ex() == (1, -1, rr, 0)
+    # autofocus plans: the second radix plan (the faster phase gradient)
+    from paper_2605_28451_amd.autofocus import AutofocusPlan
+    for mode in ("fp32", "fp16_fp32"):
+        assert AutofocusPlan(4096, 8, mode).get_tuning_ex() == (1, -1, 2, 1)
     with pytest.raises(api._lib.BfpError):
         api.FFTPlan(1024, 4, "fp16").set_tuning_ex(1, 0, 3)
 
