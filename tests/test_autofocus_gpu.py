@@ -109,20 +109,22 @@ def test_adjoint_dot_product_identity():
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("mode,with_phase,bpc", [("fp32", True, 0), ("fp16_fp32", True, 0),
-                                                 ("fp16_fp32", False, 0), ("fp16_fp32", True, 1)])
-def test_fused_image_entropy_matches_separate_passes(mode, with_phase, bpc):
+@pytest.mark.parametrize("mode,with_phase,bpc,radix_plan", [
+    ("fp32", True, 0, 1), ("fp16_fp32", True, 0, 1), ("fp16_fp32", False, 0, 1), ("fp16_fp32", True, 1, 1),
+    ("fp32", True, 0, 0), ("fp16_fp32", True, 0, 0), ("fp16_fp32", True, 3, 0)])
+def test_fused_image_entropy_matches_separate_passes(mode, with_phase, bpc, radix_plan):
     # the image of the fused pass is the image of the azimuth compression,
     # bit for bit; its statistics equal the separate reduction up to the
-    # order of the FP64 sums, and the entropy matches the FP64 oracle
+    # order of the FP64 sums, and the entropy matches the FP64 oracle,
+    # whichever radix plan is asked for (the FP32 image runs plan 0)
     need_gpu()
-    announce(f"fused image entropy mode={mode} phase={with_phase} bpc={bpc}")
+    announce(f"fused image entropy mode={mode} phase={with_phase} bpc={bpc} plan={radix_plan}")
     sc, rc_t, phi = _small_case()
     nr, npul = rc_t.shape
     fmt = api.storage_format(mode)
     rcq = scenes.quantize(rc_t, fmt)
     plan = AutofocusPlan(npul, nr, mode)
-    plan.set_tuning(1, bpc)
+    plan.set_tuning_ex(1, bpc, 2, radix_plan)
     Ha = api.filter_tensor(sc.azimuth_replica, npul, mode)
     ph = torch.tensor(phi, dtype=torch.float32, device="cuda") if with_phase else None
     rcd = upload(rcq, fmt)

@@ -129,6 +129,9 @@ def test_second_radix_plan_matches_oracle(mode, n):
                          PATH_SQNR_MIN[mode]),
             "compress_phase": (sqnr_db(oracle.compress(oracle.apply_phase(x, phi.astype(np.float64)), Hq),
                                        download(plan.azimuth_compress(xd, H, phase=ph), fmt)), PATH_SQNR_MIN[mode]),
+            "compress_phase_fp32_out": (sqnr_db(oracle.compress(oracle.apply_phase(x, phi.astype(np.float64)), Hq),
+                                                download(plan.azimuth_compress(xd, H, phase=ph, out_fp32=True),
+                                                         "fp32")), PATH_SQNR_MIN[mode]),
         }
         for k, (s, bar) in got.items():
             print(f"[measure] plan1.{mode}.n{n}.rr{rr}.{k} {s:.3f}")
