@@ -380,9 +380,11 @@ int sar_image_entropy_noalloc(const void *image, long long count, double *stats,
  * (FP32 logarithms, FP64 sums), and the workgroup partials are added in a
  * fixed order into stats (device, 3 doubles as above).  The image is the
  * one sar_azimuth_compress writes; the statistics agree with
- * sar_image_entropy up to the order of the FP64 sums.  az_plan: precision
- * BFP_FP32 or BFP_FP16_STORE_FP32_COMPUTE; n_range <= plan batch; calls on
- * one plan must not overlap. */
+ * sar_image_entropy up to the order of the FP64 sums.  A phase vector
+ * leaves exp(+i phase) in the plan's phasor table, which
+ * sar_azimuth_phase_grad can reuse.  az_plan: precision BFP_FP32 or
+ * BFP_FP16_STORE_FP32_COMPUTE; n_range <= plan batch; calls on one plan
+ * must not overlap. */
 int sar_azimuth_image_entropy(bfp_plan az_plan, const void *rc_t, void *image, const void *h_az,
                               const float *phase, int n_range, double *stats, void *stream);
 
@@ -396,10 +398,15 @@ int sar_entropy_grad(const void *image, const double *stats, const float *scale,
  * NULL), or, fused, given the image itself in g and its entropy stats
  * (L = E).  Per range bin the adjoint chain A^H = IDFT diag(conj H_a) DFT is
  * applied in FP32 and grad_phase[m] = sum_r Im(G_z[r][m] conj(z[r][m])) with
- * z = rc_t . exp(i phase) (device, n_az floats out).  az_plan: precision
- * BFP_FP32 or BFP_FP16_STORE_FP32_COMPUTE, created with BFP_FLAG_AUTOFOCUS;
- * n_range <= plan batch.  Calls on one plan must not overlap (they share
- * the plan's workspace). */
+ * z = rc_t . exp(i phase) (device, n_az floats out).  phase NULL: the
+ * plan's phasor table as the last call on the plan that took a phase vector
+ * left it (sar_azimuth_image_entropy, sar_azimuth_compress without adjoint
+ * or this call), i.e. exp(+i phase) of that call's phase as it was when the
+ * call ran, so an autofocus iteration's image and gradient share one table;
+ * BFP_EINVAL if that last call was an adjoint compression or there was none.
+ * az_plan: precision BFP_FP32 or BFP_FP16_STORE_FP32_COMPUTE, created with
+ * BFP_FLAG_AUTOFOCUS; n_range <= plan batch.  Calls on one plan must not
+ * overlap (they share the plan's workspace). */
 int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, const double *stats,
                            const void *h_az, const float *phase, float *grad_phase, int n_range,
                            void *stream);

@@ -4,8 +4,10 @@
 forward and backward passes are the HIP kernels of libbfpfft.so (the
 adjoint of the azimuth chain is the same block-floating-point chain with the
 conjugated filter).  ``entropy_and_grad`` is the fused path used in the
-optimisation loop: forward compression, entropy statistics, and the fused
-entropy-gradient + adjoint + per-pulse reduction, four kernel launches.
+optimisation loop: the phasor table, the forward compression with its
+entropy sums and their total, and, on the same phasor table, the fused
+entropy gradient + adjoint + per-pulse partial rows and their fixed-order
+sum: five kernel launches.
 """
 import ctypes
 
@@ -75,7 +77,8 @@ class AutofocusPlan(FFTPlan):
 
     def phase_grad(self, rc_t, g, h_az, phase, stats=None, out=None, stream=None):
         """dL/dphase from dL/dI (stats None) or, fused, from the image and its
-        entropy stats (L = entropy)."""
+        entropy stats (L = entropy).  phase None: the plan's phasor table as
+        the last call with a phase vector (image_and_entropy, image) left it."""
         rows = rc_t.numel() // (2 * self.n)
         _check_storage(rc_t, self.fmt, rows * self.n, "rc_t")
         _check_storage(g, "fp32", rows * self.n, "gradient/image")
@@ -125,7 +128,7 @@ class ImageEntropy(torch.autograd.Function):
 def entropy_and_grad(plan, rc_t, h_az, phase, img=None, stats=None, grad=None):
     """Fused path: (E as a device float64 scalar tensor, dE/dphase)."""
     img, stats = plan.image_and_entropy(rc_t, h_az, phase, out=img, stats=stats)
-    grad = plan.phase_grad(rc_t, img, h_az, phase, stats=stats, out=grad)
+    grad = plan.phase_grad(rc_t, img, h_az, None, stats=stats, out=grad)  # the same phasor table
     return stats[2], grad, img
 
 

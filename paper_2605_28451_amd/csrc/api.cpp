@@ -548,9 +548,11 @@ int sar_azimuth_compress(bfp_plan az_plan, const void *rc_t, void *image, const 
   const void *ph = nullptr;
   if (phase) {
     // forward: exp(+i phase) on the input; adjoint: exp(-i phase) on the output
+    az_plan->phasor_sign = 0;
     hipError_t e = bfp::launch_phasor(phase, az_plan->phasor, az_plan->n, adjoint ? 1 : 0,
                                       (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "phasor launch");
+    az_plan->phasor_sign = adjoint ? -1 : 1;
     ph = az_plan->phasor;
     if (adjoint) flags |= kPostPhasor;
   }
@@ -588,8 +590,10 @@ int sar_azimuth_image_entropy(bfp_plan az_plan, const void *rc_t, void *image, c
   if (rc_t == image) return fail(BFP_EINVAL, "rc_t and image must differ");
   const void *ph = nullptr;
   if (phase) {
+    az_plan->phasor_sign = 0;
     hipError_t e = bfp::launch_phasor(phase, az_plan->phasor, az_plan->n, 0, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "phasor launch");
+    az_plan->phasor_sign = 1;
     ph = az_plan->phasor;
   }
   int grid = 0;
@@ -645,12 +649,19 @@ int sar_azimuth_phase_grad(bfp_plan az_plan, const void *rc_t, const void *g, co
   if (!az_plan->pg_partial) return fail(BFP_EINVAL, "plan was not created with BFP_FLAG_AUTOFOCUS");
   if (n_range < 1 || n_range > az_plan->batch)
     return fail(BFP_EINVAL, "n_range outside [1, plan batch]");
-  if (!rc_t || !g || !h_az || !phase || !grad_phase) return fail(BFP_EINVAL, "NULL pointer");
+  if (!rc_t || !g || !h_az || !grad_phase) return fail(BFP_EINVAL, "NULL pointer");
+  if (!phase && az_plan->phasor_sign != 1)
+    return fail(BFP_EINVAL, "phase is NULL and no earlier call on this plan left exp(+i phase) in its table");
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != az_plan->device) return fail(BFP_EINVAL, "plan belongs to another device");
-  hipError_t e = bfp::launch_phasor(phase, az_plan->phasor, az_plan->n, 0, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "phasor launch");
+  hipError_t e = hipSuccess;
+  if (phase) {
+    az_plan->phasor_sign = 0;
+    e = bfp::launch_phasor(phase, az_plan->phasor, az_plan->n, 0, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "phasor launch");
+    az_plan->phasor_sign = 1;
+  }
   bfp::PhaseGradArgs a;
   a.gimg = g;
   a.stats = stats;

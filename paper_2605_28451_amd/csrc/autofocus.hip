@@ -312,7 +312,9 @@ __global__ void __launch_bounds__((Geometry<LOG2N, PLAN>::WG)) phase_grad_kernel
 // partial_sum_kernel adds part chunk c (parts [c P/C, (c+1) P/C)) of 64
 // columns per workgroup, 4 interleaved slices per column combined in slice
 // order, into stage[c][m]; the same kernel over the C stage rows (one chunk)
-// gives out[m].
+// gives out[m].  (One launch whose last-arriving workgroup per column block
+// adds the stage rows needs a device-scope release fence per workgroup, an
+// L2 writeback each: it made an autofocus iteration 229 instead of 162 us.)
 constexpr int kSumChunks = 16;
 
 __global__ void __launch_bounds__(256) partial_sum_kernel(const float *__restrict__ partial, int parts,

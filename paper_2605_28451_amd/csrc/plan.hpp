@@ -17,6 +17,8 @@ struct bfp_plan_s {
   void *tw_alt = nullptr;                     // rows: the second radix plan's table
   unsigned long long *nonfinite = nullptr;    // device counter
   void *phasor = nullptr;                     // n FP32 pairs (rows plans)
+  int phasor_sign = 0;  // what the last call left in phasor: 0 nothing, +1 exp(+i phi)
+                        // (forward), -1 exp(-i phi) (adjoint)
   // uneven plans
   int count = 0;
   long long total = 0;

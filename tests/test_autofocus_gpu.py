@@ -140,6 +140,51 @@ def test_fused_image_entropy_matches_separate_passes(mode, with_phase, bpc, radi
     phi32 = phi.astype(np.float32).astype(np.float64) if with_phase else np.zeros(npul)
     E_ref, _ = oracle.autofocus(rcq, Haq, phi32)
     assert abs(st2[2] - E_ref) <= (1e-4 if mode == "fp32" else 2e-3) * abs(E_ref)
+    # a call on fewer rows (another grid) and a repeat of the first call
+    # give their own sums, the repeat the same bits
+    part = nr // 2 + 3
+    img3 = torch.empty((part, npul, 2), dtype=torch.float32, device="cuda")
+    img3, st3 = plan.image_and_entropy(rcd[:part].contiguous(), Ha, ph, out=img3)
+    st3 = st3.cpu().numpy()
+    st1p = plan.entropy_stats(img1[:part].contiguous()).cpu().numpy()
+    assert torch.equal(img3, img1[:part])
+    assert abs(st3[0] - st1p[0]) <= 1e-12 * st1p[0]
+    assert abs(st3[2] - st1p[2]) <= 1e-10 * abs(st1p[2])
+    _, st4 = plan.image_and_entropy(rcd, Ha, ph)
+    assert np.array_equal(st4.cpu().numpy(), st2)
+
+
+def test_phase_grad_reuses_phasor_table():
+    # phase None: the table the image call left (exp(+i phase)); the same
+    # bits as recomputing it, on repeated calls (the partial sum's arrival
+    # counters are cleared by each column block's last workgroup), and an
+    # error where no forward call with a phase came last
+    need_gpu()
+    sc, rc_t, phi = _small_case(seed=8)
+    nr, npul = rc_t.shape
+    rcd = upload(scenes.quantize(rc_t, "fp16"), "fp16")
+    plan = AutofocusPlan(npul, nr, "fp16_fp32")
+    Ha = api.filter_tensor(sc.azimuth_replica, npul, "fp16_fp32")
+    ph = torch.tensor(phi, dtype=torch.float32, device="cuda")
+    with pytest.raises(RuntimeError, match="phase"):
+        plan.phase_grad(rcd, torch.zeros((nr, npul, 2), dtype=torch.float32, device="cuda"), Ha, None)
+    img, st = plan.image_and_entropy(rcd, Ha, ph)
+    g_tab = plan.phase_grad(rcd, img, Ha, None, stats=st)
+    g_tab2 = plan.phase_grad(rcd, img, Ha, None, stats=st)
+    g_ph = plan.phase_grad(rcd, img, Ha, ph, stats=st)
+    assert torch.equal(g_tab, g_ph) and torch.equal(g_tab2, g_ph)
+    E, g_fused, _ = entropy_and_grad(plan, rcd, Ha, ph)
+    assert torch.equal(g_fused, g_ph)
+    # fewer range bins (another grid of partial rows), then the full set again
+    part = nr // 2 + 1
+    g_part = plan.phase_grad(rcd[:part].contiguous(), img[:part].contiguous(), Ha, ph, stats=st)
+    g_ref = plan.phase_grad(rcd[:part].contiguous(), img[:part].contiguous(), Ha, ph, stats=st)
+    assert torch.equal(g_part, g_ref)
+    assert torch.equal(plan.phase_grad(rcd, img, Ha, None, stats=st), g_ph)
+    # an adjoint compression with a phase leaves exp(-i phase): refused
+    plan.azimuth_compress(rcd, Ha, phase=ph, adjoint=True)
+    with pytest.raises(RuntimeError, match="phase"):
+        plan.phase_grad(rcd, img, Ha, None, stats=st)
 
 
 @pytest.mark.parametrize("n", [1, 1000, 4096, 5000])
