@@ -179,12 +179,13 @@ def test_transposed_store_rejects_other_variants():
 
 
 @pytest.mark.parametrize("src,dst", [("fp32", "fp16"), ("fp32", "e4m3"), ("fp32", "e5m2"),
-                                     ("fp16", "e4m3"), ("e4m3", "fp32"), ("e5m2", "fp16")])
+                                     ("fp16", "e4m3"), ("fp16", "e5m2"), ("e4m3", "fp32"),
+                                     ("e5m2", "fp16")])
 def test_convert_matches_host_encoder(src, dst):
     need_gpu()
     rng = np.random.default_rng(1)
     v = rng.standard_normal(5000) * 10.0 ** rng.uniform(-6, 5, 5000)
-    v[:4] = [np.nan, -np.nan, 1e9, -1e9]  # NaN stays NaN; FP16 inf saturates in FP8
+    v[:6] = [np.nan, -np.nan, 1e9, -1e9, np.inf, -np.inf]  # NaN stays NaN; inf saturates in FP8
     x = np.empty(2500, complex)
     with np.errstate(over="ignore", invalid="ignore"):
         x.real = scenes.decode(scenes.encode(v[:2500].astype(complex), src), src).real
