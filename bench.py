@@ -464,8 +464,10 @@ def bench_uneven(mode, steps, warmup, with_sqnr=True):
     ms_eager = sorted(time_launches(lambda i: plan.execute(ins[i], out=outs[i]), sets, steps,
                                     warmup)[0] for _ in range(3))[1]
     # a replay carries a fixed cost on the device (measured ≈ 8 us beside
-    # one large kernel): 8 launches per replay, alternating the two sets
-    per_graph = 8
+    # one large kernel): 16 launches per replay, alternating the two sets
+    # (measured per launch: 152-155 us with one per replay, 148-150 with 8,
+    # 148 with 16, eager 148)
+    per_graph = 16
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
@@ -492,7 +494,7 @@ def bench_uneven(mode, steps, warmup, with_sqnr=True):
     flops = float(np.sum(5.0 * sizes * ub.log2n))
     bytes_ = 2 * x0.numel() * x0.element_size()
     res = {"mode": mode, "transforms": 20000, "ms_per_launch": ms, "ms_per_launch_eager": ms_eager,
-           "graph": "8 launches per replay over 2 rotating buffer sets (queue reset, when the grid "
+           "graph": "16 launches per replay over 2 rotating buffer sets (queue reset, when the grid "
                     "claims from the queue, and the kernel); median of 3 timed blocks",
            "autotuned_workgroups_per_cu": tuning[1], "autotune_ms": tuned_ms,
            "gflops": flops / (ms * 1e-3) / 1e9, "hbm_gbs": bytes_ / (ms * 1e-3) / 1e9,
