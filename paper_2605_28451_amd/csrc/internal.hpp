@@ -102,7 +102,11 @@ hipError_t launch_phasor(const float *phase, void *phasor, int n, int negate,
 // Autofocus: entropy statistics (S, Q, E), entropy gradient and the fused
 // adjoint + per-pulse phase-gradient reduction.
 constexpr int kEntropyBlocks = 1024;
-constexpr int kPhaseGradBlocks = 1024;  // 4 per CU on MI355X: the kernel needs the whole chip
+// grid of the phase-gradient kernel: one round of resident workgroups on
+// MI355X (their ~66 KiB of LDS allow two per CU on 256 CUs), each workgroup
+// writing one partial row per transform slot; 1024 (two rounds, twice the
+// partial rows) measured 82.5 against 78.8 us at 4096 x 4096 (radix plan 1)
+constexpr int kPhaseGradBlocks = 512;
 struct PhaseGradArgs {
   const void *gimg;      // FP32 pairs: dL/dI, or the image itself when fused
   const double *stats;   // (S, Q, E) when fused, else unused
