@@ -159,8 +159,10 @@ int fft_exec_inv_bfp_flags(bfp_plan p, const void *in, void *out, const void *fi
  * (the default of a new plan: the faster engine on MI355X at every measured
  * size; fft_autotune may still select 0).
  * blocks_per_cu: rows plans: -1 = automatic (the default of a new plan:
- * the fused compression of pure FP16 at n <= 4096 uses k = 3, everything
- * else 0), 0 = one workgroup per group of rows, k > 0 = a persistent grid of
+ * the fused compression of pure FP16 at n <= 4096 uses k = 3, or 8 from
+ * 4096 rows of 4096 points; the FP32-output image of
+ * sar_azimuth_image_entropy one round of its kernel's resident workgroups;
+ * everything else 0), 0 = one workgroup per group of rows, k > 0 = a persistent grid of
  * k workgroups per CU looping over the rows (in pure FP16 at n <= 4096 this
  * grid overlaps the next rows' loads with the current rows' transforms); uneven plans:
  * workgroups per CU of the launch, 0 = the resident maximum (the default: a

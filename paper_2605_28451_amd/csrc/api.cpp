@@ -28,8 +28,10 @@ namespace {
 // rows: the grid then outlasts one resident wave of workgroups), except for
 // the transposed store, whose XCD-aware row order wants the persistent grid
 // (a 4096 x 4096 frame with the fused corner turn: 156 us at 3, 166 us at
-// 8); every other operation one workgroup per row group (the single
-// transforms are faster at full occupancy).
+// 8); the FP32-output image with its entropy sums one round of its kernel's
+// resident workgroups (sized in the launcher); every other operation one
+// workgroup per row group (the single transforms are faster at full
+// occupancy).
 constexpr int kAutoBpc = -1;
 constexpr int kPipelinedBpc = 3;
 constexpr int kPipelinedBpcLarge = 8;
@@ -204,6 +206,9 @@ int run_rows(bfp_plan p, int op, const void *in, void *out, const void *filter,
   a.nonfinite = p->nonfinite;
   const int bpc = effective_bpc(p, op, rows, flags);
   a.grid_limit = bpc > 0 ? bpc * p->cu_count : 0;
+  // the image with its entropy sums, under automatic tuning: one round of
+  // resident workgroups (the launcher sizes it for the kernel it launches)
+  a.resident_cus = (ent_partial && p->tune_bpc == kAutoBpc) ? p->cu_count : 0;
   a.engine = p->tune_engine;
   a.rows_per_thread = p->tune_rr;
   a.ent_partial = ent_partial;

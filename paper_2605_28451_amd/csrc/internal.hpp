@@ -34,6 +34,8 @@ struct RowArgs {
   unsigned flags;        // KFlags
   unsigned long long *nonfinite;  // device counter
   int grid_limit;        // > 0: persistent grid of at most this many workgroups
+  int resident_cus;      // > 0 with grid_limit == 0 (image entropy variants): a persistent
+                         // grid of the launched kernel's resident workgroups on this many CUs
   int engine;            // 0: matrix cores where available, 1: vector ALU only
   int rows_per_thread;   // 1, or 2: the multi-row kernel where it covers the variant
   int radix_plan;        // 0, or 1: the second radix plan (tw_alt) where the multi-row
